@@ -1,0 +1,242 @@
+/*
+ * rq.h -- C ABI of librq: matrix-free evaluation of the circuit cost
+ *         f(G) = -Re Tr[U^dagger C(G)], its Riemannian gradient, Hessian-vector
+ *         products and Hessian blocks on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: arXiv 2506.23775 ("High-Performance Contraction of Quantum Circuits
+ * for Riemannian Optimization").  The trace is a sum over computational basis
+ * states |j> (eq. for the basis-vector sum in Sec. "Objective function and
+ * matrix-free evaluation"); every entry point below evaluates that sum, or a
+ * contiguous range of it, with hand-written HIP kernels.
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ *  - k qubits; qubit q is bit (k-1-q) of a basis index: qubit 0 is the most
+ *    significant tensor leg (Sec. "Gate application").
+ *  - A gate instance acts on a pair (q_hi, q_lo), q_hi != q_lo, any two
+ *    qubits.  Its 4x4 matrix is indexed by 2*bit(q_hi) + bit(q_lo).
+ *  - C(G) = G_N ... G_1: instance 0 of the pair list is applied first (Sec.
+ *    "Quantum circuits").  Repeated gates (brick-wall translation sharing,
+ *    Sec. "Brick wall circuit layout") are instances mapped to one parameter
+ *    by param_of; derivatives of a parameter sum over its instances.
+ *  - Complex numbers are interleaved (re, im).  Gate arrays are host
+ *    double [P][4][4][2], row-major.
+ *  - State slabs ("batch-interleaved"): amplitude x of basis column c is at
+ *    element x*ld + c; complex128 (RQ_C128) or complex64 (RQ_C64) elements.
+ *  - Parity mode (RQ_PARITY, Sec. "Parity-conserving gate structure"): every
+ *    gate has the pattern rows/cols {0,3} x {0,3} + {1,2} x {1,2}; entries off
+ *    the pattern are ignored (read as zero) and returned as zero.  States live
+ *    in one parity sector p and are stored compressed: amplitude x (parity p)
+ *    at row x >> 1 (the bit of qubit k-1 is implied).  A sector has 2^(k-1)
+ *    basis columns j' = j >> 1.
+ *  - Precision: states and reference columns are stored and propagated in the
+ *    target dtype; every contraction is accumulated in FP64 (per-lane partial
+ *    sums of at most 2^(tile-2) products in the state precision, then FP64).
+ *    Riemannian post-processing is FP64.
+ *
+ * Memory, streams, errors
+ * -----------------------
+ *  - The library allocates no device memory.  The caller owns the reference
+ *    columns, the workspace (size from rq_workspace_bytes) and every device
+ *    output.  Host inputs are read during the call only.
+ *  - Calls are stream-ordered and asynchronous with respect to the host:
+ *    they enqueue kernels and small host-to-device copies on exec->stream and
+ *    return; device outputs are valid once the stream reaches that point.
+ *    Two calls that run concurrently must use distinct workspaces.
+ *  - Every call returns RQ_OK (0) or an error code; rq_last_error() returns a
+ *    thread-local message for the last failing call of the calling thread.
+ *    On an argument error nothing is enqueued and no output is written.
+ */
+#ifndef RQ_H
+#define RQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define RQ_OK         0
+#define RQ_EINVAL     1   /* invalid argument (shape, pair, range, flag)      */
+#define RQ_EHIP       2   /* HIP runtime error while enqueueing               */
+#define RQ_ESPACE     3   /* workspace too small for the requested chunk      */
+#define RQ_ESINGULAR  4   /* gate (block) not invertible within tolerance     */
+
+/* ---- state / reference precision ---------------------------------------- */
+#define RQ_C128 0         /* complex double states                            */
+#define RQ_C64  1         /* complex float states, FP64 accumulation          */
+
+/* ---- circuit flags ------------------------------------------------------ */
+#define RQ_PARITY 1u      /* parity-conserving gates, sector-compressed states */
+
+/* ---- operations (for rq_workspace_bytes) -------------------------------- */
+#define RQ_OP_COST  0
+#define RQ_OP_GRAD  1
+#define RQ_OP_HVP   2
+#define RQ_OP_HESS  3
+#define RQ_OP_APPLY 4
+
+/* Circuit topology (host memory, read during a call).
+ * pairs:    [n_gates][2] (q_hi, q_lo), 0 <= q < n_qubits, q_hi != q_lo.
+ * param_of: [n_gates] parameter of each instance in [0, n_params), or NULL
+ *           for the identity map (then n_params must equal n_gates).
+ * n_qubits: 2..30 (4..31 with RQ_PARITY). */
+typedef struct rq_circuit {
+  int32_t n_qubits;
+  int32_t n_gates;
+  int32_t n_params;
+  uint32_t flags;
+  const int32_t *pairs;
+  const int32_t *param_of;
+} rq_circuit;
+
+/* Target U given by its columns U|j> on the device (Sec. "Objective function
+ * and matrix-free evaluation": the bra side of summand j is (U|j>)^*).
+ * General mode: ref[x*ld + j] = U[x][j], x, j < 2^k.
+ * Parity mode:  ref[s*sector_stride + x'*ld + j'] = U[x][j] for the sector s
+ *               blocks (U conserves parity), x', j' < 2^(k-1).
+ * dtype is also the state precision of the evaluation. */
+typedef struct rq_target {
+  int32_t dtype;
+  int32_t reserved;
+  const void *ref;
+  int64_t ld;
+  int64_t sector_stride;
+} rq_target;
+
+/* Range of basis states of the trace sum.  General mode: j in
+ * [begin, begin+count) of [0, 2^k), sector must be -1.  Parity mode: sector
+ * 0 or 1 and j' in [begin, begin+count) of [0, 2^(k-1)), or sector -1 with
+ * begin 0 and count 2^(k-1) for both sectors.  A NULL range is the full
+ * trace.  count 0 is allowed (all outputs are then the empty sum, projected). */
+typedef struct rq_range {
+  int32_t sector;
+  int32_t reserved;
+  int64_t begin;
+  int64_t count;
+} rq_range;
+
+/* Execution resources.  workspace: device memory of at least
+ * rq_workspace_bytes(circuit, op, dtype, chunk) bytes, 256-byte aligned.
+ * chunk: basis columns per sweep (multiple of 64, >= 64).  stream: a
+ * hipStream_t (NULL = default stream). */
+typedef struct rq_exec {
+  void *workspace;
+  size_t workspace_bytes;
+  int64_t chunk;
+  void *stream;
+} rq_exec;
+
+/* Bytes of workspace needed for op (RQ_OP_*) with states of dtype and the
+ * given chunk.  Returns 0 for invalid arguments (see rq_last_error). */
+size_t rq_workspace_bytes(const rq_circuit *circuit, int32_t op, int32_t dtype,
+                          int64_t chunk);
+
+/* f = -Re sum_{j in range} <j| U^dagger C(G) |j>   (eq. for the target
+ * function and its basis-vector sum).
+ * gates: host double [P][4][4][2].  d_f: device double[1]. */
+int rq_cost(const rq_circuit *circuit, const rq_target *target,
+            const double *gates, const rq_range *range, const rq_exec *exec,
+            double *d_f);
+
+/* Gradient (Sec. "Efficient gradient and Hessian computation": forward pass
+ * with cached states, backward pass with transposed gates, gate-hole
+ * contractions of Sec. "Gate gradient as a gate hole").
+ * Outputs (device, each nullable):
+ *   d_f      double[1]            f as in rq_cost
+ *   d_egrad  double[P][4][4][2]   Euclidean gradient  -conj(dh/dG_p)  (gradient
+ *                                 convention d_x f + i d_y f, Sec. "Riemannian
+ *                                 optimization"), summed over instances
+ *   d_rgrad  double[P][4][4][2]   Riemannian gradient P_G(egrad), with the
+ *                                 projection P_V X = V skew(V^dagger X). */
+int rq_grad(const rq_circuit *circuit, const rq_target *target,
+            const double *gates, const rq_range *range, const rq_exec *exec,
+            double *d_f, double *d_egrad, double *d_rgrad);
+
+/* Hessian-vector product along a tangent direction (appendix on
+ * Hessian-vector products: forward-mode directed gradient, then
+ * backpropagation; Riemannian Hessian Hess f[X] = nabla_X grad f with the
+ * Levi-Civita connection of Sec. "Riemannian optimization").
+ * dir: host double [P][4][4][2], a tangent vector X_p = G_p A_p (A_p anti-
+ * Hermitian); it is used as given (not re-projected).
+ * Outputs (device, nullable): f, egrad, rgrad as rq_grad, and
+ *   d_ehvp  double[P][4][4][2]   D egrad[X] = -conj(d/deps dh/dG_p)
+ *   d_rhvp  double[P][4][4][2]   P_G(D egrad[X] - X sym(G^dagger egrad)). */
+int rq_hvp(const rq_circuit *circuit, const rq_target *target,
+           const double *gates, const double *dir, const rq_range *range,
+           const rq_exec *exec, double *d_f, double *d_egrad, double *d_rgrad,
+           double *d_ehvp, double *d_rhvp);
+
+/* All pairwise Hessian blocks (Sec. "Efficient gradient and Hessian
+ * computation": gate-hole application to a state, second forward pass of the
+ * 16-entry state array (8 in parity mode), contraction at every later gate).
+ * Outputs (device, nullable):
+ *   d_f, d_egrad, d_rgrad as rq_grad;
+ *   d_hess_holo  double[P][d][P][d][2]  holomorphic second derivatives
+ *                d^2 h / dG_p[e] dG_q[e'] summed over instances, d = 16 entries
+ *                (a,b) row-major, or d = 8 pattern entries in parity mode in
+ *                the order (0,0),(0,3),(3,0),(3,3),(1,1),(1,2),(2,1),(2,2);
+ *   d_hess_real  double[P*d][P*d]   Riemannian Hessian in the orthonormal
+ *                tangent basis X_{p,mu} = G_p A_mu documented in
+ *                rq_tangent_basis (d = 16, or 8 in parity mode). */
+int rq_hess_blocks(const rq_circuit *circuit, const rq_target *target,
+                   const double *gates, const rq_range *range,
+                   const rq_exec *exec, double *d_f, double *d_egrad,
+                   double *d_rgrad, double *d_hess_holo, double *d_hess_real);
+
+/* Bytes of workspace needed by rq_hess_blocks for states of dtype and the
+ * given chunk (multiple of 64).  Returns 0 for invalid arguments. */
+size_t rq_hess_workspace_bytes(const rq_circuit *circuit, int32_t dtype,
+                               int64_t chunk);
+
+/* Apply the circuit to a slab of states in place (Sec. "Gate application"):
+ * states[x*ld + c] for c < n_states, x < 2^k (general) or sector-compressed
+ * x' < 2^(k-1) of the given sector (parity mode; sector must then be 0/1,
+ * otherwise -1).  Any number of columns; ld >= n_states.  Used to prepare
+ * target columns U|j> from a gate list (e.g. a Trotter circuit).
+ * exec: workspace of rq_workspace_bytes(circuit, RQ_OP_APPLY, dtype, 0)
+ * bytes (gate coefficients) and the stream; exec->chunk is ignored. */
+int rq_apply_circuit(const rq_circuit *circuit, const double *gates,
+                     void *d_states, int64_t n_states, int64_t ld,
+                     int32_t dtype, int32_t sector, const rq_exec *exec);
+
+/* One trust-region step on the host in FP64 (Sec. "Riemannian optimization":
+ * quadratic model, truncated CG of Absil et al. Algorithm 11, polar retraction
+ * R_V(xi) = q_polar(V + xi) per gate).  Host inputs: gates [P][4][4][2], the
+ * Riemannian gradient g and Hessian H in the basis of rq_tangent_basis
+ * (n = P*d), radius delta.  Host outputs: eta[n] (step), cand [P][4][4][2]
+ * (retracted gates), model_decrease (m(0) - m(eta)), stop (0 converged,
+ * 1 boundary, 2 negative curvature, 3 iteration limit, 4 zero gradient).
+ * Constants: theta = 1, kappa = 0.1. */
+int rq_tr_step(int32_t n_params, uint32_t flags, const double *gates,
+               const double *g, const double *H, double delta, double *eta,
+               double *cand, double *model_decrease, int32_t *stop);
+
+/* Trust-region acceptance and radius update after evaluating f at the
+ * candidate: rho = (f0 - f1) / model_decrease; accepted = rho > 0.1; radius
+ * quartered if rho < 1/4, doubled (capped at delta_bar) if rho > 3/4 and the
+ * step norm eta_norm equals delta.  Host scalars only. */
+int rq_tr_accept(double f0, double f1, double model_decrease, double delta,
+                 double delta_bar, double eta_norm, double *new_delta,
+                 int32_t *accepted, double *rho);
+
+/* Orthonormal tangent basis A_mu (host output double[d][4][4][2]) used by
+ * rq_hess_blocks / rq_tr_step: X_{p,mu} = G_p A_mu.  Returns d (16 or 8). */
+int rq_tangent_basis(uint32_t flags, double *basis);
+
+/* Diagnostics: gate instances per sweep pass chosen by the scheduler for op
+ * and dtype.  pass_of[n_gates] (host) receives the pass index of every
+ * instance; returns the number of passes (< 0 on error). */
+int rq_plan_passes(const rq_circuit *circuit, int32_t op, int32_t dtype,
+                   int32_t *pass_of);
+
+const char *rq_strerror(int status);
+const char *rq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RQ_H */

@@ -1,0 +1,590 @@
+// C ABI of librq: argument validation, gate preprocessing, workspace layout
+// and the sweep schedule of rq_cost / rq_grad / rq_hvp / rq_apply_circuit.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rq.h"
+#include "rq_internal.h"
+#include "rq_plan.h"
+
+using namespace rqk;
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+thread_local std::vector<char> g_stage;  // host staging of per-call device data
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+constexpr int kParityIdx[8] = {0, 3, 12, 15, 5, 6, 9, 10};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Tile qubits per (precision, op): the largest tile whose register footprint
+// keeps the sweep kernel free of scratch spills (states held per lane:
+// cost/apply 1, grad 2, HVP 4).
+int nt_max(int is_double, int op) {
+  if (!is_double) {
+    switch (op) {
+      case OP_COST: case OP_APPLY: case OP_GRAD: return 5;
+      case OP_HVP: return 4;
+    }
+  } else {
+    switch (op) {
+      case OP_COST: case OP_APPLY: return 5;
+      case OP_GRAD: return 4;
+      case OP_HVP: return 3;
+    }
+  }
+  return 2;
+}
+
+int tile_nt(int kq, int is_double, int op) {
+  const int m = nt_max(is_double, op);
+  return kq >= m ? m : 2;
+}
+
+int kernel_op(int32_t op) {
+  switch (op) {
+    case RQ_OP_COST: return OP_COST;
+    case RQ_OP_GRAD: return OP_GRAD;
+    case RQ_OP_HVP: return OP_HVP;
+    case RQ_OP_APPLY: return OP_APPLY;
+    case RQ_OP_HESS: return OP_GRAD;
+  }
+  return -1;
+}
+
+int entries(int op, bool parity) {
+  const int nt1 = parity ? 16 : 32;
+  if (op == OP_HVP) return 2 * nt1;
+  if (op == OP_GRAD) return nt1;
+  return 0;
+}
+
+int check_circuit(const rq_circuit *c) {
+  if (!c) return fail(RQ_EINVAL, "circuit is NULL");
+  const bool parity = c->flags & RQ_PARITY;
+  if (c->flags & ~RQ_PARITY) return fail(RQ_EINVAL, "unknown circuit flag");
+  const int kmin = parity ? 4 : 2;
+  if (c->n_qubits < kmin || c->n_qubits > 30 + (parity ? 1 : 0))
+    return fail(RQ_EINVAL, "n_qubits out of range");
+  if (c->n_gates < 1 || c->n_gates > 32767) return fail(RQ_EINVAL, "n_gates out of range [1, 32767]");
+  if (!c->pairs) return fail(RQ_EINVAL, "pairs is NULL");
+  if (c->n_params < 1) return fail(RQ_EINVAL, "n_params must be >= 1");
+  if (!c->param_of && c->n_params != c->n_gates)
+    return fail(RQ_EINVAL, "param_of NULL requires n_params == n_gates");
+  for (int g = 0; g < c->n_gates; ++g) {
+    const int a = c->pairs[2 * g], b = c->pairs[2 * g + 1];
+    if (a < 0 || b < 0 || a >= c->n_qubits || b >= c->n_qubits || a == b)
+      return fail(RQ_EINVAL, "gate " + std::to_string(g) + ": invalid qubit pair");
+    if (c->param_of) {
+      const int p = c->param_of[g];
+      if (p < 0 || p >= c->n_params)
+        return fail(RQ_EINVAL, "gate " + std::to_string(g) + ": param_of out of range");
+    }
+  }
+  return RQ_OK;
+}
+
+int param_of(const rq_circuit *c, int g) { return c->param_of ? c->param_of[g] : g; }
+
+struct Layout {
+  int op = 0, is_double = 0, parity = 0, kq = 0, nt = 0, ne = 0, nbuf = 0;
+  int64_t chunk = 0, rows = 0;
+  size_t esize = 0;
+  std::vector<PlanPass> plan;
+  size_t off_coef = 0, off_g64 = 0, off_d64 = 0, off_pof = 0, off_slots = 0, off_fslots = 0,
+         off_tsum = 0, off_fsum = 0, off_states = 0, state_bytes = 0, upload_bytes = 0, total = 0;
+};
+
+int make_layout(const rq_circuit *c, int32_t op_pub, int32_t dtype, int64_t chunk, Layout &L) {
+  int st = check_circuit(c);
+  if (st) return st;
+  if (dtype != RQ_C128 && dtype != RQ_C64) return fail(RQ_EINVAL, "dtype must be RQ_C128 or RQ_C64");
+  const int op = kernel_op(op_pub);
+  if (op < 0) return fail(RQ_EINVAL, "unknown op");
+  if (op_pub != RQ_OP_APPLY && (chunk < 64 || chunk % 64))
+    return fail(RQ_EINVAL, "chunk must be a positive multiple of 64");
+  L.op = op;
+  L.is_double = dtype == RQ_C128;
+  L.parity = (c->flags & RQ_PARITY) != 0;
+  L.kq = L.parity ? c->n_qubits - 1 : c->n_qubits;
+  L.nt = tile_nt(L.kq, L.is_double, op);
+  L.ne = entries(op, L.parity);
+  if (op != OP_APPLY && ((int64_t(1) << (L.kq - L.nt)) * ((chunk + 63) / 64)) >= (int64_t(1) << 31))
+    return fail(RQ_EINVAL, "problem too large for one sweep grid (reduce chunk)");
+  L.esize = L.is_double ? 16 : 8;
+  L.chunk = chunk;
+  L.rows = int64_t(1) << L.kq;
+  std::string err;
+  if (!plan_passes(c->n_qubits, c->n_gates, c->pairs, L.parity, L.nt, kMaxGates, L.plan, err))
+    return fail(RQ_EINVAL, err);
+  const int N = c->n_gates, P = c->n_params;
+  const int np = (int)L.plan.size();
+  const int nst = op == OP_HVP ? 2 : 1;
+  if (op == OP_COST)
+    L.nbuf = np > 1 ? 1 : 0;
+  else if (op == OP_APPLY)
+    L.nbuf = 0;
+  else
+    L.nbuf = nst * (np - 1) + nst;
+  size_t o = 0;
+  L.off_coef = o;
+  o = align256(o + size_t(N) * kCoefStride * L.esize);
+  L.off_g64 = o;
+  o = align256(o + size_t(P) * 32 * sizeof(double));
+  L.off_d64 = o;
+  o = align256(o + size_t(P) * 32 * sizeof(double));
+  L.off_pof = o;
+  o = align256(o + size_t(N) * sizeof(int32_t));
+  L.upload_bytes = o;
+  if (op != OP_APPLY) {
+    L.off_slots = o;
+    o = align256(o + size_t(N) * L.ne * kMaxWaves * sizeof(double));
+    L.off_fslots = o;
+    o = align256(o + size_t(kMaxWaves) * sizeof(double));
+    L.off_tsum = o;
+    o = align256(o + size_t(N) * L.ne * sizeof(double));
+    L.off_fsum = o;
+    o = align256(o + sizeof(double));
+  }
+  L.off_states = o;
+  L.state_bytes = op == OP_APPLY ? 0 : size_t(L.rows) * size_t(chunk) * L.esize;
+  o = align256(o + size_t(L.nbuf) * L.state_bytes);
+  L.total = o;
+  return RQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Gate preprocessing (host, FP64)
+// ---------------------------------------------------------------------------
+void load_gate(const double *src, int p, bool parity, cd *M) {
+  for (int e = 0; e < 16; ++e) M[e] = cd(src[(size_t(p) * 16 + e) * 2], src[(size_t(p) * 16 + e) * 2 + 1]);
+  if (parity) {
+    bool keep[16] = {false};
+    for (int c = 0; c < 8; ++c) keep[kParityIdx[c]] = true;
+    for (int e = 0; e < 16; ++e)
+      if (!keep[e]) M[e] = 0.0;
+  }
+}
+
+double fro(const cd *M, int n) {
+  double s = 0;
+  for (int i = 0; i < n * n; ++i) s += std::norm(M[i]);
+  return std::sqrt(s);
+}
+
+// Gauss-Jordan inverse with partial pivoting; false if singular or badly
+// conditioned (||A||_F ||A^-1||_F > 1e8).
+bool invert(const cd *A, cd *Ai, int n) {
+  cd a[16], b[16];
+  for (int i = 0; i < n * n; ++i) {
+    a[i] = A[i];
+    b[i] = (i / n == i % n) ? 1.0 : 0.0;
+  }
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::abs(a[r * n + col]) > std::abs(a[piv * n + col])) piv = r;
+    if (std::abs(a[piv * n + col]) == 0.0) return false;
+    if (piv != col)
+      for (int j = 0; j < n; ++j) {
+        std::swap(a[piv * n + j], a[col * n + j]);
+        std::swap(b[piv * n + j], b[col * n + j]);
+      }
+    const cd d = 1.0 / a[col * n + col];
+    for (int j = 0; j < n; ++j) {
+      a[col * n + j] *= d;
+      b[col * n + j] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const cd f = a[r * n + col];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        a[r * n + j] -= f * a[col * n + j];
+        b[r * n + j] -= f * b[col * n + j];
+      }
+    }
+  }
+  for (int i = 0; i < n * n; ++i) Ai[i] = b[i];
+  return fro(A, n) * fro(Ai, n) <= 1e8;
+}
+
+bool invert_gate(const cd *G, bool parity, cd *Gi) {
+  if (!parity) return invert(G, Gi, 4);
+  for (int e = 0; e < 16; ++e) Gi[e] = 0.0;
+  const int blk[2][2] = {{0, 3}, {1, 2}};
+  for (int b = 0; b < 2; ++b) {
+    cd m[4], mi[4];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) m[2 * i + j] = G[4 * blk[b][i] + blk[b][j]];
+    if (!invert(m, mi, 2)) return false;
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) Gi[4 * blk[b][i] + blk[b][j]] = mi[2 * i + j];
+  }
+  return true;
+}
+
+void matmul4(const cd *A, const cd *B, cd *C) {
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      cd s = 0;
+      for (int k = 0; k < 4; ++k) s += A[4 * i + k] * B[4 * k + j];
+      C[4 * i + j] = s;
+    }
+}
+
+template <typename R>
+void put_block(char *dst, const cd *M, bool parity) {
+  R *d = reinterpret_cast<R *>(dst);
+  if (parity) {
+    for (int c = 0; c < 8; ++c) {
+      d[2 * c] = (R)M[kParityIdx[c]].real();
+      d[2 * c + 1] = (R)M[kParityIdx[c]].imag();
+    }
+    for (int c = 8; c < 16; ++c) d[2 * c] = d[2 * c + 1] = R(0);
+  } else {
+    for (int e = 0; e < 16; ++e) {
+      d[2 * e] = (R)M[e].real();
+      d[2 * e + 1] = (R)M[e].imag();
+    }
+  }
+}
+
+// Stage per-instance coefficient blocks, FP64 gates/directions and param_of.
+int prepare_upload(const rq_circuit *c, const Layout &L, const double *gates, const double *dir) {
+  const int N = c->n_gates, P = c->n_params;
+  const bool parity = L.parity;
+  g_stage.assign(L.upload_bytes, 0);
+  std::vector<cd> G(size_t(P) * 16), Gi(size_t(P) * 16), Z(size_t(P) * 16), GiZ(size_t(P) * 16);
+  for (int p = 0; p < P; ++p) {
+    load_gate(gates, p, parity, &G[size_t(p) * 16]);
+    if (!invert_gate(&G[size_t(p) * 16], parity, &Gi[size_t(p) * 16]))
+      return fail(RQ_ESINGULAR, "gate parameter " + std::to_string(p) + " is not invertible");
+    if (dir) {
+      load_gate(dir, p, parity, &Z[size_t(p) * 16]);
+      matmul4(&Gi[size_t(p) * 16], &Z[size_t(p) * 16], &GiZ[size_t(p) * 16]);
+    }
+  }
+  const size_t blk = size_t(16) * L.esize;
+  for (int l = 0; l < N; ++l) {
+    const int p = param_of(c, l);
+    char *d = g_stage.data() + L.off_coef + size_t(l) * kCoefStride * L.esize;
+    const cd *src[4] = {&G[size_t(p) * 16], &Gi[size_t(p) * 16], &Z[size_t(p) * 16],
+                        &GiZ[size_t(p) * 16]};
+    for (int m = 0; m < 4; ++m) {
+      if (L.is_double)
+        put_block<double>(d + m * blk, src[m], parity);
+      else
+        put_block<float>(d + m * blk, src[m], parity);
+    }
+  }
+  double *g64 = reinterpret_cast<double *>(g_stage.data() + L.off_g64);
+  double *d64 = reinterpret_cast<double *>(g_stage.data() + L.off_d64);
+  for (int p = 0; p < P; ++p)
+    for (int e = 0; e < 16; ++e) {
+      g64[(size_t(p) * 16 + e) * 2] = G[size_t(p) * 16 + e].real();
+      g64[(size_t(p) * 16 + e) * 2 + 1] = G[size_t(p) * 16 + e].imag();
+      d64[(size_t(p) * 16 + e) * 2] = Z[size_t(p) * 16 + e].real();
+      d64[(size_t(p) * 16 + e) * 2 + 1] = Z[size_t(p) * 16 + e].imag();
+    }
+  int32_t *pof = reinterpret_cast<int32_t *>(g_stage.data() + L.off_pof);
+  for (int l = 0; l < N; ++l) pof[l] = param_of(c, l);
+  return RQ_OK;
+}
+
+int hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) return fail(RQ_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return RQ_OK;
+}
+
+void fill_pass(PassArgs &a, const PlanPass &pp, const Layout &L) {
+  a.kq = L.kq;
+  a.qmask = pp.qmask;
+  for (int b = 0; b < 8; ++b) a.pos[b] = pp.pos[b];
+  a.ngates = (int)pp.gates.size();
+  for (int g = 0; g < a.ngates; ++g) a.gates[g] = pp.gates[g];
+}
+
+int grid_for(const Layout &L, int ncols, int &items, int &ncg) {
+  ncg = (ncols + 63) / 64;
+  const int64_t tiles = int64_t(1) << (L.kq - L.nt);
+  const int64_t it = tiles * ncg;
+  items = (int)it;
+  const int64_t waves = it < kMaxWaves ? it : kMaxWaves;
+  return (int)((waves + 3) / 4);
+}
+
+struct Range {
+  int sectors[2];
+  int nsec;
+  int64_t begin, count;
+};
+
+int check_range(const rq_circuit *c, const Layout &L, const rq_range *r, Range &R) {
+  const int64_t ncol = int64_t(1) << L.kq;
+  if (!r) {
+    R.begin = 0;
+    R.count = ncol;
+    if (L.parity) {
+      R.nsec = 2;
+      R.sectors[0] = 0;
+      R.sectors[1] = 1;
+    } else {
+      R.nsec = 1;
+      R.sectors[0] = 0;
+    }
+    return RQ_OK;
+  }
+  if (r->begin < 0 || r->count < 0 || r->begin + r->count > ncol)
+    return fail(RQ_EINVAL, "basis range out of bounds");
+  R.begin = r->begin;
+  R.count = r->count;
+  if (!L.parity) {
+    if (r->sector != -1) return fail(RQ_EINVAL, "sector must be -1 without RQ_PARITY");
+    R.nsec = 1;
+    R.sectors[0] = 0;
+  } else if (r->sector == -1) {
+    if (r->begin != 0 || r->count != ncol)
+      return fail(RQ_EINVAL, "sector -1 requires the full range of both sectors");
+    R.nsec = 2;
+    R.sectors[0] = 0;
+    R.sectors[1] = 1;
+  } else if (r->sector == 0 || r->sector == 1) {
+    R.nsec = 1;
+    R.sectors[0] = r->sector;
+  } else {
+    return fail(RQ_EINVAL, "sector must be -1, 0 or 1");
+  }
+  (void)c;
+  return RQ_OK;
+}
+
+// The trace sweep shared by cost / grad / HVP.
+int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, const double *dir,
+              const rq_range *range, const rq_exec *ex, int op_pub, double *d_f, double *d_egrad,
+              double *d_rgrad, double *d_ehvp, double *d_rhvp) {
+  if (!t || !t->ref) return fail(RQ_EINVAL, "target or target->ref is NULL");
+  if (!ex || !ex->workspace) return fail(RQ_EINVAL, "exec or workspace is NULL");
+  if (!gates) return fail(RQ_EINVAL, "gates is NULL");
+  if (op_pub == RQ_OP_HVP && !dir) return fail(RQ_EINVAL, "dir is NULL");
+  Layout L;
+  int st = make_layout(c, op_pub, t->dtype, ex->chunk, L);
+  if (st) return st;
+  if (ex->workspace_bytes < L.total)
+    return fail(RQ_ESPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  if (reinterpret_cast<uintptr_t>(ex->workspace) & 255)
+    return fail(RQ_EINVAL, "workspace must be 256-byte aligned");
+  Range R;
+  st = check_range(c, L, range, R);
+  if (st) return st;
+  const int64_t ncol = int64_t(1) << L.kq;
+  if (t->ld < ncol && R.count > 0) return fail(RQ_EINVAL, "target ld smaller than the column count");
+  st = prepare_upload(c, L, gates, dir);
+  if (st) return st;
+
+  char *ws = static_cast<char *>(ex->workspace);
+  hipStream_t s = static_cast<hipStream_t>(ex->stream);
+  st = hip_check(hipMemcpyAsync(ws, g_stage.data(), L.upload_bytes, hipMemcpyHostToDevice, s),
+                 "upload");
+  if (st) return st;
+  double *slots = reinterpret_cast<double *>(ws + L.off_slots);
+  double *fslots = reinterpret_cast<double *>(ws + L.off_fslots);
+  double *tsum = reinterpret_cast<double *>(ws + L.off_tsum);
+  double *fsum = reinterpret_cast<double *>(ws + L.off_fsum);
+  const int N = c->n_gates;
+  if (launch_zero(slots, int64_t(N) * L.ne * kMaxWaves, s) || launch_zero(fslots, kMaxWaves, s))
+    return fail(RQ_EHIP, "zero kernel launch failed");
+
+  const int np = (int)L.plan.size();
+  const int nst = L.op == OP_HVP ? 2 : 1;
+  char *states = ws + L.off_states;
+  auto buf = [&](int i) -> void * { return states + size_t(i) * L.state_bytes; };
+  // COST: one in-place buffer.  GRAD/HVP: checkpoint after pass p (p < np-1)
+  // at buffers nst*p (+1 tangent); phi (+dphi) at nst*(np-1).
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.coef = ws + L.off_coef;
+  a.slots = slots;
+  a.fslots = fslots;
+  a.nslots = kMaxWaves;
+  a.ne = L.ne;
+  a.ld = L.chunk;
+  a.ld_ref = t->ld;
+
+  for (int si = 0; si < R.nsec; ++si) {
+    const int sector = R.sectors[si];
+    a.sector = sector;
+    a.ref = static_cast<const char *>(t->ref) + size_t(sector) * size_t(t->sector_stride) * L.esize;
+    for (int64_t j0 = R.begin; j0 < R.begin + R.count; j0 += L.chunk) {
+      const int ncols = (int)std::min<int64_t>(L.chunk, R.begin + R.count - j0);
+      int items, ncg;
+      const int grid = grid_for(L, ncols, items, ncg);
+      a.col0 = j0;
+      a.ncols = ncols;
+      a.ncg = ncg;
+      a.n_items = items;
+      // forward passes
+      for (int p = 0; p + 1 < np; ++p) {
+        fill_pass(a, L.plan[p], L);
+        if (L.op == OP_COST) {
+          a.src_psi = p == 0 ? nullptr : buf(0);
+          a.dst_psi = buf(0);
+        } else {
+          a.src_psi = p == 0 ? nullptr : buf(nst * (p - 1));
+          a.src_dpsi = p == 0 ? nullptr : (nst == 2 ? buf(nst * (p - 1) + 1) : nullptr);
+          a.dst_psi = buf(nst * p);
+          a.dst_dpsi = nst == 2 ? buf(nst * p + 1) : nullptr;
+        }
+        if (launch_pass(L.is_double, L.nt, L.parity, L.op, ST_FWD, a, grid, s))
+          return fail(RQ_EHIP, "forward pass launch failed");
+      }
+      // last pass: forward, overlap with U|j>, first backward pass
+      fill_pass(a, L.plan[np - 1], L);
+      if (L.op == OP_COST) {
+        a.src_psi = np == 1 ? nullptr : buf(0);
+      } else {
+        a.src_psi = np == 1 ? nullptr : buf(nst * (np - 2));
+        a.src_dpsi = (np == 1 || nst == 1) ? nullptr : buf(nst * (np - 2) + 1);
+        a.phi = buf(nst * (np - 1));
+        a.dphi = nst == 2 ? buf(nst * (np - 1) + 1) : nullptr;
+        a.store_phi = np > 1;
+      }
+      if (launch_pass(L.is_double, L.nt, L.parity, L.op, ST_LAST, a, grid, s))
+        return fail(RQ_EHIP, "last pass launch failed");
+      if (L.op == OP_COST) continue;
+      for (int p = np - 2; p >= 0; --p) {
+        fill_pass(a, L.plan[p], L);
+        a.ckpt_psi = buf(nst * p);
+        a.ckpt_dpsi = nst == 2 ? buf(nst * p + 1) : nullptr;
+        a.store_phi = p > 0;
+        if (launch_pass(L.is_double, L.nt, L.parity, L.op, ST_BWD, a, grid, s))
+          return fail(RQ_EHIP, "backward pass launch failed");
+      }
+    }
+  }
+  if (L.op != OP_COST && launch_reduce(slots, N, L.ne, kMaxWaves, tsum, s))
+    return fail(RQ_EHIP, "reduce launch failed");
+  if (launch_reduce(fslots, 1, 1, kMaxWaves, fsum, s)) return fail(RQ_EHIP, "reduce launch failed");
+  const double *g64 = reinterpret_cast<const double *>(ws + L.off_g64);
+  const double *d64 = reinterpret_cast<const double *>(ws + L.off_d64);
+  const int32_t *pof = reinterpret_cast<const int32_t *>(ws + L.off_pof);
+  if (launch_post(L.op, L.parity, c->n_params, N, pof, tsum, L.ne, fsum, kMaxWaves, g64, d64, d_f,
+                  d_egrad, d_rgrad, d_ehvp, d_rhvp, s))
+    return fail(RQ_EHIP, "post-processing launch failed");
+  return RQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rq_workspace_bytes(const rq_circuit *circuit, int32_t op, int32_t dtype, int64_t chunk) {
+  if (op == RQ_OP_HESS) {
+    g_err = "rq_workspace_bytes: RQ_OP_HESS uses rq_hess_workspace_bytes";
+  }
+  Layout L;
+  if (make_layout(circuit, op == RQ_OP_HESS ? RQ_OP_GRAD : op, dtype, op == RQ_OP_APPLY ? 64 : chunk, L))
+    return 0;
+  return L.total;
+}
+
+int rq_cost(const rq_circuit *circuit, const rq_target *target, const double *gates,
+            const rq_range *range, const rq_exec *exec, double *d_f) {
+  return run_sweep(circuit, target, gates, nullptr, range, exec, RQ_OP_COST, d_f, nullptr,
+                   nullptr, nullptr, nullptr);
+}
+
+int rq_grad(const rq_circuit *circuit, const rq_target *target, const double *gates,
+            const rq_range *range, const rq_exec *exec, double *d_f, double *d_egrad,
+            double *d_rgrad) {
+  return run_sweep(circuit, target, gates, nullptr, range, exec, RQ_OP_GRAD, d_f, d_egrad,
+                   d_rgrad, nullptr, nullptr);
+}
+
+int rq_hvp(const rq_circuit *circuit, const rq_target *target, const double *gates,
+           const double *dir, const rq_range *range, const rq_exec *exec, double *d_f,
+           double *d_egrad, double *d_rgrad, double *d_ehvp, double *d_rhvp) {
+  return run_sweep(circuit, target, gates, dir, range, exec, RQ_OP_HVP, d_f, d_egrad, d_rgrad,
+                   d_ehvp, d_rhvp);
+}
+
+int rq_apply_circuit(const rq_circuit *circuit, const double *gates, void *d_states,
+                     int64_t n_states, int64_t ld, int32_t dtype, int32_t sector,
+                     const rq_exec *exec) {
+  if (!gates || !exec || !exec->workspace) return fail(RQ_EINVAL, "gates/exec/workspace is NULL");
+  Layout L;
+  int st = make_layout(circuit, RQ_OP_APPLY, dtype, 64, L);
+  if (st) return st;
+  if (n_states < 0 || ld < n_states || ld < 1) return fail(RQ_EINVAL, "invalid n_states / ld");
+  if (n_states > 0 && !d_states) return fail(RQ_EINVAL, "states is NULL");
+  if (L.parity ? (sector != 0 && sector != 1) : sector != -1)
+    return fail(RQ_EINVAL, "sector must be 0/1 with RQ_PARITY, -1 otherwise");
+  if (exec->workspace_bytes < L.total)
+    return fail(RQ_ESPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  if (n_states > (int64_t(1) << 30) ||
+      (int64_t(1) << (L.kq - L.nt)) * ((n_states + 63) / 64) >= (int64_t(1) << 31))
+    return fail(RQ_EINVAL, "too many states for one sweep grid");
+  st = prepare_upload(circuit, L, gates, nullptr);
+  if (st) return st;
+  if (n_states == 0) return RQ_OK;
+  char *ws = static_cast<char *>(exec->workspace);
+  hipStream_t s = static_cast<hipStream_t>(exec->stream);
+  st = hip_check(hipMemcpyAsync(ws, g_stage.data(), L.upload_bytes, hipMemcpyHostToDevice, s),
+                 "upload");
+  if (st) return st;
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.coef = ws + L.off_coef;
+  a.ld = ld;
+  a.sector = L.parity ? sector : 0;
+  a.ncols = (int)n_states;
+  int items, ncg;
+  const int grid = grid_for(L, (int)n_states, items, ncg);
+  a.ncg = ncg;
+  a.n_items = items;
+  for (const PlanPass &pp : L.plan) {
+    fill_pass(a, pp, L);
+    a.src_psi = d_states;
+    a.dst_psi = d_states;
+    if (launch_pass(L.is_double, L.nt, L.parity, OP_APPLY, ST_FWD, a, grid, s))
+      return fail(RQ_EHIP, "apply pass launch failed");
+  }
+  return RQ_OK;
+}
+
+int rq_plan_passes(const rq_circuit *circuit, int32_t op, int32_t dtype, int32_t *pass_of) {
+  Layout L;
+  int st = make_layout(circuit, op == RQ_OP_HESS ? RQ_OP_GRAD : op, dtype, 64, L);
+  if (st) return -st;
+  if (pass_of)
+    for (size_t p = 0; p < L.plan.size(); ++p)
+      for (const GateRef &g : L.plan[p].gates) pass_of[g.inst] = (int32_t)p;
+  return (int)L.plan.size();
+}
+
+const char *rq_strerror(int status) {
+  switch (status) {
+    case RQ_OK: return "ok";
+    case RQ_EINVAL: return "invalid argument";
+    case RQ_EHIP: return "HIP runtime error";
+    case RQ_ESPACE: return "workspace too small";
+    case RQ_ESINGULAR: return "gate not invertible";
+  }
+  return "unknown status";
+}
+
+const char *rq_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Internal declarations shared by the host side of librq and its kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace rqk {
+
+// Maximum gate instances in one sweep pass.
+constexpr int kMaxGates = 16;
+// Threads per block of the sweep kernels (4 wavefronts of 64 lanes).
+constexpr int kBlock = 256;
+// Maximum number of wavefronts of a sweep grid; also the number of FP64
+// partial-sum slots per accumulated quantity.
+constexpr int kMaxWaves = 2048;
+// Complex coefficients stored per gate instance:
+//   [ 0,16) G      [16,32) G^-1      [32,48) Z      [48,64) G^-1 Z
+// dense gates row-major 4x4; parity gates the 8 pattern entries in the order
+// (0,0),(0,3),(3,0),(3,3),(1,1),(1,2),(2,1),(2,2).
+constexpr int kCoefStride = 64;
+
+enum Mode { MODE_DENSE = 0, MODE_PARITY = 1 };
+enum Op { OP_COST = 0, OP_GRAD = 1, OP_HVP = 2, OP_APPLY = 3 };
+enum Stage { ST_FWD = 0, ST_LAST = 1, ST_BWD = 2 };
+
+// One gate of a pass.  kind 0: both qubits in the tile (local bits h, l);
+// kind 1: parity mode, q_lo is the implied qubit k-1 (h = local bit of q_hi);
+// kind 2: parity mode, q_hi is the implied qubit (h = local bit of q_lo).
+struct GateRef {
+  int16_t inst;
+  int16_t kind;
+  int16_t h;
+  int16_t l;
+};
+
+struct PassArgs {
+  const void *coef;        // per-instance coefficients (state precision)
+  const void *src_psi;     // FWD / LAST input states (NULL: one-hot |j>)
+  const void *src_dpsi;    // HVP tangent input (NULL: zero)
+  void *dst_psi;           // FWD output (checkpoint / in-place apply)
+  void *dst_dpsi;
+  const void *ckpt_psi;    // BWD: states after this pass
+  const void *ckpt_dpsi;
+  void *phi;               // BWD in/out, LAST out
+  void *dphi;
+  const void *ref;         // LAST: target columns U|j> (sector block)
+  double *slots;           // FP64 partials [inst][entry][slot]
+  double *fslots;          // FP64 partials of f [slot]
+  int64_t ld;              // row stride of the chunk slabs (elements)
+  int64_t ld_ref;          // row stride of ref (elements)
+  int64_t col0;            // basis column of chunk column 0
+  int32_t ncols;           // valid columns of the chunk
+  int32_t ncg;             // column groups of 64
+  int32_t kq;              // explicit qubits (k, or k-1 in parity mode)
+  int32_t n_items;         // tiles * column groups
+  uint32_t qmask;          // bit positions (in the row index) of the tile
+  int32_t sector;          // parity sector p (0 in general mode)
+  int32_t ngates;
+  int32_t nslots;
+  int32_t store_phi;
+  int32_t ne;              // FP64 entries per instance in slots
+  int32_t pos[8];          // row bit position of local tile bit b
+  GateRef gates[kMaxGates];
+};
+
+// Host-side launchers (defined in rq_kernels.hip).
+int launch_pass(int is_double, int nt, int mode, int op, int stage,
+                const PassArgs &a, int grid, void *stream);
+int launch_reduce(const double *slots, int n_inst, int ne, int nslots,
+                  double *out, void *stream);
+int launch_zero(double *p, int64_t n, void *stream);
+int launch_post(int op, int parity, int n_params, int n_inst, const int32_t *param_of,
+                const double *tsum, int ne, const double *fslots, int nslots,
+                const double *gates64, const double *dir64, double *d_f,
+                double *d_egrad, double *d_rgrad, double *d_ehvp, double *d_rhvp,
+                void *stream);
+
+}  // namespace rqk

@@ -1,0 +1,423 @@
+"""Thin ctypes binding of librq (argument marshalling only).
+
+Every computation runs in librq's HIP kernels; this module only converts
+numpy / torch arguments to the C structures of ``include/rq.h``, owns the
+device workspace and returns device results as torch tensors.  It raises
+``RuntimeError`` when the library is missing or a call fails (there is no
+fallback implementation).
+
+Conventions follow ``include/rq.h``: gates are complex [P, 4, 4] arrays
+indexed by 2*bit(q_hi) + bit(q_lo); qubit 0 is the most significant bit of a
+basis index; in parity mode states are sector-compressed (row x >> 1).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librq.so")
+
+RQ_OK, RQ_EINVAL, RQ_EHIP, RQ_ESPACE, RQ_ESINGULAR = 0, 1, 2, 3, 4
+RQ_C128, RQ_C64 = 0, 1
+RQ_PARITY = 1
+RQ_OP_COST, RQ_OP_GRAD, RQ_OP_HVP, RQ_OP_HESS, RQ_OP_APPLY = 0, 1, 2, 3, 4
+
+
+class _Circuit(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("n_gates", C.c_int32), ("n_params", C.c_int32),
+                ("flags", C.c_uint32), ("pairs", C.POINTER(C.c_int32)),
+                ("param_of", C.POINTER(C.c_int32))]
+
+
+class _Target(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("reserved", C.c_int32), ("ref", C.c_void_p),
+                ("ld", C.c_int64), ("sector_stride", C.c_int64)]
+
+
+class _Range(C.Structure):
+    _fields_ = [("sector", C.c_int32), ("reserved", C.c_int32), ("begin", C.c_int64),
+                ("count", C.c_int64)]
+
+
+class _Exec(C.Structure):
+    _fields_ = [("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("chunk", C.c_int64), ("stream", C.c_void_p)]
+
+
+_lib = None
+
+EXPORTS = ["rq_workspace_bytes", "rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks",
+           "rq_hess_workspace_bytes", "rq_apply_circuit", "rq_tr_step", "rq_tr_accept",
+           "rq_tangent_basis", "rq_plan_passes", "rq_strerror", "rq_last_error"]
+
+
+def lib():
+    """Load librq.so (built in-tree by ``paper_2506_23775_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not found: run paper_2506_23775_amd/build.py "
+                           "(there is no fallback implementation)")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    L.rq_workspace_bytes.restype = C.c_size_t
+    L.rq_workspace_bytes.argtypes = [C.POINTER(_Circuit), C.c_int32, C.c_int32, C.c_int64]
+    L.rq_hess_workspace_bytes.restype = C.c_size_t
+    L.rq_hess_workspace_bytes.argtypes = [C.POINTER(_Circuit), C.c_int32, C.c_int64]
+    common = [C.POINTER(_Circuit), C.POINTER(_Target), dp]
+    L.rq_cost.argtypes = common + [C.POINTER(_Range), C.POINTER(_Exec), P]
+    L.rq_grad.argtypes = common + [C.POINTER(_Range), C.POINTER(_Exec), P, P, P]
+    L.rq_hvp.argtypes = common + [dp, C.POINTER(_Range), C.POINTER(_Exec), P, P, P, P, P]
+    L.rq_hess_blocks.argtypes = common + [C.POINTER(_Range), C.POINTER(_Exec), P, P, P, P, P]
+    L.rq_apply_circuit.argtypes = [C.POINTER(_Circuit), dp, P, C.c_int64, C.c_int64,
+                                   C.c_int32, C.c_int32, C.POINTER(_Exec)]
+    L.rq_tr_step.argtypes = [C.c_int32, C.c_uint32, dp, dp, dp, C.c_double, dp, dp, dp,
+                             C.POINTER(C.c_int32)]
+    L.rq_tr_accept.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                               C.c_double, dp, C.POINTER(C.c_int32), dp]
+    L.rq_tangent_basis.argtypes = [C.c_uint32, dp]
+    L.rq_plan_passes.argtypes = [C.POINTER(_Circuit), C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    L.rq_strerror.restype = C.c_char_p
+    L.rq_last_error.restype = C.c_char_p
+    for name in ["rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks", "rq_apply_circuit",
+                 "rq_tr_step", "rq_tr_accept", "rq_tangent_basis", "rq_plan_passes"]:
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class RQError(RuntimeError):
+    def __init__(self, status, where):
+        L = lib()
+        msg = L.rq_last_error().decode()
+        super().__init__(f"{where}: {L.rq_strerror(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _check(status, where):
+    if status != RQ_OK:
+        raise RQError(status, where)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _gates_host(g) -> np.ndarray:
+    g = g.detach().cpu().numpy() if isinstance(g, torch.Tensor) else np.asarray(g)
+    g = np.ascontiguousarray(g.astype(np.complex128)).reshape(-1, 4, 4)
+    return g
+
+
+# ---------------------------------------------------------------------------
+# Circuit / target descriptions
+# ---------------------------------------------------------------------------
+
+class Circuit:
+    """Gate topology: k qubits, pairs [(q_hi, q_lo)], optional param_of."""
+
+    def __init__(self, k: int, pairs: Sequence, param_of=None, n_params: Optional[int] = None,
+                 parity: bool = False):
+        self.k = int(k)
+        self.pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        self.n_gates = self.pairs.shape[0]
+        if param_of is None:
+            self.param_of = None
+            self.n_params = self.n_gates if n_params is None else int(n_params)
+        else:
+            self.param_of = np.ascontiguousarray(np.asarray(param_of, dtype=np.int32))
+            self.n_params = int(self.param_of.max()) + 1 if n_params is None else int(n_params)
+        self.parity = bool(parity)
+        self._c = _Circuit(self.k, self.n_gates, self.n_params, RQ_PARITY if parity else 0,
+                           self.pairs.ctypes.data_as(C.POINTER(C.c_int32)),
+                           None if self.param_of is None
+                           else self.param_of.ctypes.data_as(C.POINTER(C.c_int32)))
+
+    @property
+    def kq(self):
+        return self.k - 1 if self.parity else self.k
+
+    @property
+    def ncols(self):
+        return 1 << self.kq
+
+    def plan(self, op: int, dtype: int):
+        pass_of = np.zeros(self.n_gates, dtype=np.int32)
+        n = lib().rq_plan_passes(C.byref(self._c), op, dtype,
+                                 pass_of.ctypes.data_as(C.POINTER(C.c_int32)))
+        if n < 0:
+            raise RQError(-n, "rq_plan_passes")
+        return n, pass_of
+
+
+def torch_dtype(dtype: int):
+    return torch.complex128 if dtype == RQ_C128 else torch.complex64
+
+
+def sector_rows(k: int, p: int) -> np.ndarray:
+    """Full basis indices of the compressed rows x' of parity sector p."""
+    xp = np.arange(1 << (k - 1), dtype=np.int64)
+    par = np.zeros_like(xp)
+    v = xp.copy()
+    while np.any(v):
+        par ^= v & 1
+        v >>= 1
+    return (xp << 1) | (par ^ p)
+
+
+@dataclass
+class Target:
+    """Device target columns.  ``ref``: general [2^k, 2^k] (U[x][j]) or parity
+    [2, 2^(k-1), 2^(k-1)] sector blocks, complex64 / complex128 on cuda."""
+
+    ref: torch.Tensor
+    dtype: int
+    parity: bool
+
+    def struct(self):
+        if self.parity:
+            ld = self.ref.shape[2]
+            ss = self.ref.shape[1] * self.ref.shape[2]
+        else:
+            ld = self.ref.shape[1]
+            ss = 0
+        return _Target(self.dtype, 0, self.ref.data_ptr(), ld, ss)
+
+    @staticmethod
+    def from_dense(U: np.ndarray, dtype: int = RQ_C128, parity: bool = False, device="cuda"):
+        U = np.asarray(U)
+        k = int(np.log2(U.shape[0]))
+        if parity:
+            blocks = np.stack([U[np.ix_(sector_rows(k, p), sector_rows(k, p))] for p in (0, 1)])
+            t = torch.from_numpy(np.ascontiguousarray(blocks)).to(torch_dtype(dtype))
+        else:
+            t = torch.from_numpy(np.ascontiguousarray(U)).to(torch_dtype(dtype))
+        return Target(t.to(device), dtype, parity)
+
+
+# ---------------------------------------------------------------------------
+# Workspace
+# ---------------------------------------------------------------------------
+
+class Workspace:
+    """Caller-owned device workspace (the library allocates no device memory)."""
+
+    def __init__(self, nbytes: int, device="cuda"):
+        self.buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        self.offset = (-base) % 256
+        self.ptr = base + self.offset
+        self.nbytes = int(nbytes)
+
+
+_ws_cache = {}
+
+
+def _workspace(nbytes: int, key=None) -> Workspace:
+    key = key or (torch.cuda.current_device(),)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.nbytes < nbytes:
+        _ws_cache.pop(key, None)
+        ws = Workspace(nbytes)
+        _ws_cache[key] = ws
+    return ws
+
+
+def default_chunk(circuit: Circuit, op: int, dtype: int, ncols: int,
+                  budget_bytes: int = 24 << 30) -> int:
+    """Largest power-of-two chunk (>= 64, <= padded column count) whose
+    workspace fits the budget."""
+    L = lib()
+    top = max(64, 1 << int(np.ceil(np.log2(max(ncols, 64)))))
+    chunk = top
+    while chunk > 64:
+        need = L.rq_workspace_bytes(C.byref(circuit._c), op, dtype, chunk)
+        if need and need <= budget_bytes:
+            break
+        chunk //= 2
+    return chunk
+
+
+def _exec(circuit: Circuit, op: int, dtype: int, chunk, workspace, stream):
+    L = lib()
+    if chunk is None:
+        chunk = default_chunk(circuit, op, dtype, circuit.ncols)
+    if op == RQ_OP_HESS:
+        need = L.rq_hess_workspace_bytes(C.byref(circuit._c), dtype, chunk)
+    else:
+        need = L.rq_workspace_bytes(C.byref(circuit._c), op, dtype, chunk)
+    if need == 0:
+        raise RQError(RQ_EINVAL, "rq_workspace_bytes")
+    ws = workspace if workspace is not None else _workspace(need)
+    if ws.nbytes < need:
+        raise RuntimeError(f"workspace too small: {ws.nbytes} < {need}")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _Exec(ws.ptr, ws.nbytes, chunk, s.cuda_stream), ws
+
+
+def _range(rng):
+    if rng is None:
+        return None
+    sector, begin, count = rng
+    return C.byref(_Range(sector, 0, begin, count))
+
+
+def _out(shape, want=True):
+    if not want:
+        return None
+    return torch.zeros(shape, dtype=torch.float64, device="cuda")
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _cplx(t):
+    return None if t is None else torch.view_as_complex(t)
+
+
+# ---------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def rq_cost(circuit: Circuit, target: Target, gates, range=None, chunk=None, workspace=None,
+            stream=None) -> torch.Tensor:
+    g = _gates_host(gates)
+    ex, ws = _exec(circuit, RQ_OP_COST, target.dtype, chunk, workspace, stream)
+    f = _out((1,))
+    t = target.struct()
+    _check(lib().rq_cost(C.byref(circuit._c), C.byref(t), _dptr(g), _range(range), C.byref(ex),
+                         _ptr(f)), "rq_cost")
+    return f[0]
+
+
+def rq_grad(circuit: Circuit, target: Target, gates, range=None, chunk=None, workspace=None,
+            stream=None):
+    """Returns (f, egrad [P,4,4] complex, rgrad [P,4,4] complex) on the device."""
+    g = _gates_host(gates)
+    ex, ws = _exec(circuit, RQ_OP_GRAD, target.dtype, chunk, workspace, stream)
+    P = circuit.n_params
+    f, eg, rg = _out((1,)), _out((P, 4, 4, 2)), _out((P, 4, 4, 2))
+    t = target.struct()
+    _check(lib().rq_grad(C.byref(circuit._c), C.byref(t), _dptr(g), _range(range), C.byref(ex),
+                         _ptr(f), _ptr(eg), _ptr(rg)), "rq_grad")
+    return f[0], _cplx(eg), _cplx(rg)
+
+
+def rq_hvp(circuit: Circuit, target: Target, gates, direction, range=None, chunk=None,
+           workspace=None, stream=None):
+    """Returns (f, egrad, rgrad, ehvp, rhvp) on the device."""
+    g = _gates_host(gates)
+    d = _gates_host(direction)
+    ex, ws = _exec(circuit, RQ_OP_HVP, target.dtype, chunk, workspace, stream)
+    P = circuit.n_params
+    f = _out((1,))
+    eg, rg, eh, rh = (_out((P, 4, 4, 2)) for _ in (0, 1, 2, 3))
+    t = target.struct()
+    _check(lib().rq_hvp(C.byref(circuit._c), C.byref(t), _dptr(g), _dptr(d), _range(range),
+                        C.byref(ex), _ptr(f), _ptr(eg), _ptr(rg), _ptr(eh), _ptr(rh)), "rq_hvp")
+    return f[0], _cplx(eg), _cplx(rg), _cplx(eh), _cplx(rh)
+
+
+def rq_hess_blocks(circuit: Circuit, target: Target, gates, range=None, chunk=None,
+                   workspace=None, stream=None, holomorphic=True):
+    """Returns (f, egrad, rgrad, hess_holo [P,d,P,d] complex or None,
+    hess_real [P*d, P*d]) on the device."""
+    g = _gates_host(gates)
+    ex, ws = _exec(circuit, RQ_OP_HESS, target.dtype, chunk, workspace, stream)
+    P = circuit.n_params
+    d = 8 if circuit.parity else 16
+    f, eg, rg = _out((1,)), _out((P, 4, 4, 2)), _out((P, 4, 4, 2))
+    hh = _out((P, d, P, d, 2), holomorphic)
+    hr = _out((P * d, P * d))
+    t = target.struct()
+    _check(lib().rq_hess_blocks(C.byref(circuit._c), C.byref(t), _dptr(g), _range(range),
+                                C.byref(ex), _ptr(f), _ptr(eg), _ptr(rg), _ptr(hh), _ptr(hr)),
+           "rq_hess_blocks")
+    return f[0], _cplx(eg), _cplx(rg), _cplx(hh), hr
+
+
+def rq_apply_circuit(circuit: Circuit, gates, states: torch.Tensor, dtype: Optional[int] = None,
+                     sector: int = -1, workspace=None, stream=None) -> torch.Tensor:
+    """Apply the circuit in place to ``states`` ([rows, n] complex on cuda,
+    column c = one state).  Returns ``states``."""
+    if dtype is None:
+        dtype = RQ_C128 if states.dtype == torch.complex128 else RQ_C64
+    if states.dtype != torch_dtype(dtype) or states.dim() != 2 or states.stride(1) != 1:
+        raise ValueError("states must be a row-major [rows, n] tensor of the given dtype")
+    g = _gates_host(gates)
+    L = lib()
+    need = L.rq_workspace_bytes(C.byref(circuit._c), RQ_OP_APPLY, dtype, 0)
+    if need == 0:
+        raise RQError(RQ_EINVAL, "rq_workspace_bytes")
+    ws = workspace if workspace is not None else _workspace(need, key=("apply",))
+    s = stream if stream is not None else torch.cuda.current_stream()
+    ex = _Exec(ws.ptr, ws.nbytes, 0, s.cuda_stream)
+    _check(L.rq_apply_circuit(C.byref(circuit._c), _dptr(g), states.data_ptr(), states.shape[1],
+                              states.stride(0), dtype, sector, C.byref(ex)), "rq_apply_circuit")
+    return states
+
+
+def rq_tangent_basis(parity: bool = False) -> np.ndarray:
+    d = 8 if parity else 16
+    out = np.zeros((d, 4, 4), dtype=np.complex128)
+    n = lib().rq_tangent_basis(RQ_PARITY if parity else 0, _dptr(out))
+    assert n == d
+    return out
+
+
+def rq_tr_step(gates, g: np.ndarray, H: np.ndarray, delta: float, parity: bool = False):
+    """Host FP64 truncated-CG step and polar retraction; returns
+    (eta, candidate gates [P,4,4], model_decrease, stop_code)."""
+    G = _gates_host(gates)
+    P = G.shape[0]
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
+    H = np.ascontiguousarray(np.asarray(H, dtype=np.float64))
+    eta = np.zeros_like(g)
+    cand = np.zeros_like(G)
+    md = C.c_double(0)
+    stop = C.c_int32(0)
+    _check(lib().rq_tr_step(P, RQ_PARITY if parity else 0, _dptr(G), _dptr(g), _dptr(H),
+                            float(delta), _dptr(eta), _dptr(cand), C.byref(md), C.byref(stop)),
+           "rq_tr_step")
+    return eta, cand, md.value, stop.value
+
+
+def rq_tr_accept(f0, f1, model_decrease, delta, delta_bar, eta_norm):
+    nd = C.c_double(0)
+    acc = C.c_int32(0)
+    rho = C.c_double(0)
+    _check(lib().rq_tr_accept(f0, f1, model_decrease, delta, delta_bar, eta_norm, C.byref(nd),
+                              C.byref(acc), C.byref(rho)), "rq_tr_accept")
+    return nd.value, bool(acc.value), rho.value
+
+
+def build_trotter_target(k: int, gate_list, dtype: int = RQ_C128, parity: bool = True,
+                         device="cuda") -> Target:
+    """Target columns U|j> for every basis state, built on the device by
+    applying a gate list (e.g. a Trotter circuit) to the identity columns with
+    rq_apply_circuit.  Parity mode returns the two sector blocks."""
+    pairs = [p for p, _ in gate_list]
+    gates = np.stack([G for _, G in gate_list])
+    circ = Circuit(k, pairs, parity=parity)
+    td = torch_dtype(dtype)
+    if parity:
+        n = 1 << (k - 1)
+        ref = torch.zeros((2, n, n), dtype=td, device=device)
+        for p in (0, 1):
+            ref[p].fill_diagonal_(1.0)
+            rq_apply_circuit(circ, gates, ref[p], dtype=dtype, sector=p)
+    else:
+        n = 1 << k
+        ref = torch.eye(n, dtype=td, device=device)
+        rq_apply_circuit(circ, gates, ref, dtype=dtype, sector=-1)
+    return Target(ref, dtype, parity)
