@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput of the matrix-free f + gradient + HVP hot path on one MI355X.
+
+Workload (default): 16 qubits = 8-site spinful Fermi-Hubbard ring (J=1, U=4,
+interleaved spins), target U = Strang Trotter circuit (200 steps, t = 1.0)
+built on the GPU with rq_apply_circuit; 7-layer brick wall with one shared
+parity-conserving gate per layer (56 instances, 7 parameters); the trace runs
+over both parity sectors (2 x 2^15 basis states, sector-compressed states).
+One step = one evaluation: f, Riemannian gradient of all gates and one
+Hessian-vector product along a seeded tangent direction, summed over all
+2^16 basis states, target columns resident in HBM.
+
+Prints one JSON line (see README section of the design doc for the fields).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0           # MI355X HBM3E, GB/s
+PEAK_VALU_TFLOPS = 78.6         # 256 CU x 64 lanes x FMA x 2.4 GHz (FP32 unpacked = FP64)
+
+METRIC = "f+grad+HVP evals/s at n=16 (FP32 vs FP64 states), HBM GB/s, p50/p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_run(rq, torch, circ, target, prob, steps, warmup, chunk):
+    ws_need = rq.lib().rq_workspace_bytes(rq.C.byref(circ._c), rq.RQ_OP_HVP, target.dtype, chunk)
+    ws = rq.Workspace(ws_need)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        rq.rq_hvp(circ, target, prob.gates, prob.direction, chunk=chunk, workspace=ws)
+    torch.cuda.synchronize()
+    rq.rq_profile_read()                     # drop anything recorded so far
+    rq.rq_profile_enable(True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for i in range(steps):
+        evs[i][0].record(stream)
+        out = rq.rq_hvp(circ, target, prob.gates, prob.direction, chunk=chunk, workspace=ws)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rq.rq_profile_enable(False)
+    prof = rq.rq_profile_read()
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    res = [x.detach().cpu().numpy() for x in out]
+    del ws
+    return dict(seconds=t1 - t0, lat_ms=lat, prof=prof, result=res, ws_bytes=ws_need)
+
+
+def roofline(prof, key):
+    st = prof[key]
+    n = st["launches"]
+    avg_s = st["ms"] / n / 1e3
+    by = st["bytes"] / n
+    fl = st["flops"] / n
+    gbs = by / avg_s / 1e9
+    tfl = fl / avg_s / 1e12
+    hbm_frac = gbs / PEAK_HBM_GBS
+    alu_frac = tfl / PEAK_VALU_TFLOPS
+    if hbm_frac >= alu_frac:
+        return dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(hbm_frac, 4), traffic=None,
+                    kernel=f"k_pass {key[0]}/{key[1]}", avg_launch_ms=round(avg_s * 1e3, 4),
+                    alu=dict(achieved=round(tfl, 2), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
+                             frac=round(alu_frac, 4)))
+    return dict(bound="alu", achieved=round(tfl, 2), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
+                frac=round(alu_frac, 4), traffic=None,
+                kernel=f"k_pass {key[0]}/{key[1]}", avg_launch_ms=round(avg_s * 1e3, 4),
+                hbm=dict(achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                         frac=round(hbm_frac, 4)))
+
+
+def cpu_baseline(prob, ncols=2, budget_s=15.0):
+    """The FP64 oracle timed on the host on a bounded sample: f, gradient and
+    HVP contributions of `ncols` basis states of sector 0, extrapolated to the
+    full 2^k-term trace (every summand costs the same)."""
+    import oracle as O
+    k = prob.k
+    cols = O.sector_columns(k, 0)[:ncols]
+    E = np.zeros((1 << k, ncols), dtype=np.complex128)
+    E[cols, np.arange(ncols)] = 1.0
+    for pair, G in prob.trotter:             # U|j> for the sample (untimed setup)
+        E = O.apply_gate(E, k, pair, G)
+    inst = prob.gates[prob.param_of]
+    Z = prob.direction[prob.param_of]
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        O.tangent_T(k, prob.pairs, inst, Z, E, cols)
+        O.cost(k, prob.pairs, inst, E, cols)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    per_col = dt / ncols
+    cores = len(os.sched_getaffinity(0))
+    return dict(value=1.0 / (per_col * (1 << k)), unit="evals/s", cores=cores, kind="oracle",
+                sample=f"{ncols} basis states of sector 0 x {reps} repetitions "
+                       f"({dt * reps:.1f} s), extrapolated x{(1 << k) // ncols}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--chunk", type=int, default=4096)
+    ap.add_argument("--chunk128", type=int, default=2048)
+    ap.add_argument("--trotter-steps", type=int, default=200)
+    ap.add_argument("--no-c128", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 2 GiB device copy first (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the "
+              "multi-GPU sharding of the basis sum is described in DESIGN.md but not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as w
+    from paper_2506_23775_amd import rq
+
+    rq.lib()
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.complex64, device="cuda")   # 2 GiB
+        y = x.clone()
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {x.numel() * 8} bytes read and written")
+        del x, y
+    prob = w.make_problem(3, trotter_steps=args.trotter_steps)
+    circ = rq.Circuit(prob.k, prob.pairs, param_of=prob.param_of, parity=True)
+    log(f"[bench] building target: {len(prob.trotter)} Trotter gates on 2 x 2^15 columns")
+    t0 = time.perf_counter()
+    tgt128 = rq.build_trotter_target(prob.k, prob.trotter, dtype=rq.RQ_C128, parity=True)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"[bench] target built in {setup_s:.1f} s")
+    tgt64 = rq.Target(tgt128.ref.to(torch.complex64), rq.RQ_C64, True)
+    if args.no_c128:
+        tgt128 = None
+        torch.cuda.empty_cache()
+
+    log("[bench] c64 timed run")
+    r64 = gpu_run(rq, torch, circ, tgt64, prob, args.steps, args.warmup, args.chunk)
+    ms64 = r64["seconds"] / args.steps * 1e3
+    log(f"[bench] c64: {ms64:.1f} ms/eval")
+    out = {"metric": METRIC, "value": round(args.steps / r64["seconds"], 4), "unit": "evals/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms64, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+           "data": "synthetic (seeded Haar parity gates, Trotter target built on device)",
+           "config": {"workload": "cfg3: k=16 spinful Fermi-Hubbard ring (8 sites, J=1, U=4, "
+                                  "t=1), Strang-200 target, 7-layer brick wall, 7 shared "
+                                  "parity gates (56 instances), 2 x 2^15 parity sectors, "
+                                  "c64 states + FP64 accumulation",
+                      "k": prob.k, "layers": prob.n_layers, "gates": prob.n_gates,
+                      "params": prob.n_params, "basis_states": 1 << prob.k,
+                      "chunk": args.chunk, "target_setup_s": round(setup_s, 2)}}
+    out["latency_ms"] = {"p50": round(float(np.percentile(r64["lat_ms"], 50)), 3),
+                         "p99": round(float(np.percentile(r64["lat_ms"], 99)), 3)}
+    kern = {f"{k[0]}/{k[1]}": dict(ms=round(v["ms"], 3), launches=v["launches"],
+                                   GBps=round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1),
+                                   TFLOPs=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2))
+            for k, v in r64["prof"].items()}
+    out["kernels_c64"] = kern
+    tot_bytes = sum(v["bytes"] for v in r64["prof"].values())
+    out["hbm_GBps_algorithmic"] = round(tot_bytes / r64["seconds"] / 1e9, 1)
+    dom = max(r64["prof"].items(), key=lambda kv: kv[1]["ms"])[0]
+    out["roofline"] = roofline(r64["prof"], dom)
+
+    if tgt128 is not None:
+        log("[bench] c128 timed run")
+        r128 = gpu_run(rq, torch, circ, tgt128, prob, args.steps, args.warmup, args.chunk128)
+        ms128 = r128["seconds"] / args.steps * 1e3
+        err = {}
+        names = ["f", "egrad", "rgrad", "ehvp", "rhvp"]
+        for n, a, b in zip(names, r64["result"], r128["result"]):
+            nb = np.linalg.norm(b)
+            err[n] = float(np.linalg.norm(a - b) / (nb if nb else 1.0))
+        err["f_abs_over_2k"] = float(abs(r64["result"][0] - r128["result"][0]) / (1 << prob.k))
+        out["c128"] = {"value": round(args.steps / r128["seconds"], 4), "unit": "evals/s",
+                       "ms_per_step": round(ms128, 3), "chunk": args.chunk128,
+                       "latency_ms": {"p50": round(float(np.percentile(r128["lat_ms"], 50)), 3),
+                                      "p99": round(float(np.percentile(r128["lat_ms"], 99)), 3)}}
+        out["fp32_speedup_vs_fp64"] = round(ms128 / ms64, 3)
+        out["c64_rel_error_vs_c128"] = {k: float(f"{v:.3e}") for k, v in err.items()}
+        dom128 = max(r128["prof"].items(), key=lambda kv: kv[1]["ms"])[0]
+        out["roofline_c128"] = roofline(r128["prof"], dom128)
+
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

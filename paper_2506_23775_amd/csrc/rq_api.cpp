@@ -5,6 +5,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -113,8 +114,8 @@ int make_layout(const rq_circuit *c, int32_t op_pub, int32_t dtype, int64_t chun
   if (dtype != RQ_C128 && dtype != RQ_C64) return fail(RQ_EINVAL, "dtype must be RQ_C128 or RQ_C64");
   const int op = kernel_op(op_pub);
   if (op < 0) return fail(RQ_EINVAL, "unknown op");
-  if (op_pub != RQ_OP_APPLY && (chunk < 64 || chunk % 64))
-    return fail(RQ_EINVAL, "chunk must be a positive multiple of 64");
+  if (op_pub != RQ_OP_APPLY && (chunk < 64 || chunk % 64 || chunk > (int64_t(1) << 26)))
+    return fail(RQ_EINVAL, "chunk must be a multiple of 64 in [64, 2^26]");
   L.op = op;
   L.is_double = dtype == RQ_C128;
   L.parity = (c->flags & RQ_PARITY) != 0;
@@ -304,6 +305,73 @@ int prepare_upload(const rq_circuit *c, const Layout &L, const double *gates, co
   return RQ_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Launch profiling (HIP events on the launch stream)
+// ---------------------------------------------------------------------------
+struct ProfRec {
+  hipEvent_t a, b;
+  int kind;
+  double bytes, flops;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t prof_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Algorithmic flops per amplitude per gate (FMA = 2 flops) of the minimal
+// method: forward psi (+ dpsi), backward phi (+ dphi) and the hole
+// contractions (+ their tangents); dense 4x4 gates, parity 2x2 blocks.
+double flops_per_amp_gate(int op, int stage, bool parity) {
+  double fwd = 0, bwd = 0;
+  switch (op) {
+    case OP_COST: case OP_APPLY: fwd = 32; break;
+    case OP_GRAD: fwd = 32; bwd = 64; break;
+    case OP_HVP: fwd = 96; bwd = 192; break;
+  }
+  const double s = parity ? 0.5 : 1.0;
+  if (stage == ST_FWD) return s * fwd;
+  if (stage == ST_BWD) return s * bwd;
+  return s * (fwd + bwd);
+}
+
+int launch_prof(int is_double, int nt, int parity, int op, int stage, const PassArgs &a, int grid,
+                hipStream_t s, double slabs) {
+  ProfRec r{};
+  bool on;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    on = g_prof_on;
+    if (on) {
+      r.a = prof_event();
+      r.b = prof_event();
+    }
+  }
+  if (on && r.a) hipEventRecord(r.a, s);
+  const int st = launch_pass(is_double, nt, parity, op, stage, a, grid, s);
+  if (on && r.b) {
+    hipEventRecord(r.b, s);
+    int64_t tiles = int64_t(1) << (a.kq - nt);
+    const double amps = double(tiles) * double(1 << nt) * double(a.ncols);
+    r.kind = 3 * op + stage;
+    r.bytes = amps * slabs * (is_double ? 16.0 : 8.0);
+    r.flops = amps * double(a.ngates) * flops_per_amp_gate(op, stage, parity != 0);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back(r);
+  }
+  return st;
+}
+
 int hip_check(hipError_t e, const char *what) {
   if (e != hipSuccess) return fail(RQ_EHIP, std::string(what) + ": " + hipGetErrorString(e));
   return RQ_OK;
@@ -447,7 +515,8 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
           a.dst_psi = buf(nst * p);
           a.dst_dpsi = nst == 2 ? buf(nst * p + 1) : nullptr;
         }
-        if (launch_pass(L.is_double, L.nt, L.parity, L.op, ST_FWD, a, grid, s))
+        if (launch_prof(L.is_double, L.nt, L.parity, L.op, ST_FWD, a, grid, s,
+                        (p > 0 ? nst : 0) + nst))
           return fail(RQ_EHIP, "forward pass launch failed");
       }
       // last pass: forward, overlap with U|j>, first backward pass
@@ -461,7 +530,8 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
         a.dphi = nst == 2 ? buf(nst * (np - 1) + 1) : nullptr;
         a.store_phi = np > 1;
       }
-      if (launch_pass(L.is_double, L.nt, L.parity, L.op, ST_LAST, a, grid, s))
+      if (launch_prof(L.is_double, L.nt, L.parity, L.op, ST_LAST, a, grid, s,
+                      (np > 1 ? nst : 0) + 1 + (L.op != OP_COST && np > 1 ? nst : 0)))
         return fail(RQ_EHIP, "last pass launch failed");
       if (L.op == OP_COST) continue;
       for (int p = np - 2; p >= 0; --p) {
@@ -469,7 +539,8 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
         a.ckpt_psi = buf(nst * p);
         a.ckpt_dpsi = nst == 2 ? buf(nst * p + 1) : nullptr;
         a.store_phi = p > 0;
-        if (launch_pass(L.is_double, L.nt, L.parity, L.op, ST_BWD, a, grid, s))
+        if (launch_prof(L.is_double, L.nt, L.parity, L.op, ST_BWD, a, grid, s,
+                        2 * nst + (p > 0 ? nst : 0)))
           return fail(RQ_EHIP, "backward pass launch failed");
       }
     }
@@ -533,7 +604,7 @@ int rq_apply_circuit(const rq_circuit *circuit, const double *gates, void *d_sta
     return fail(RQ_EINVAL, "sector must be 0/1 with RQ_PARITY, -1 otherwise");
   if (exec->workspace_bytes < L.total)
     return fail(RQ_ESPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
-  if (n_states > (int64_t(1) << 30) ||
+  if (n_states > (int64_t(1) << 26) ||
       (int64_t(1) << (L.kq - L.nt)) * ((n_states + 63) / 64) >= (int64_t(1) << 31))
     return fail(RQ_EINVAL, "too many states for one sweep grid");
   st = prepare_upload(circuit, L, gates, nullptr);
@@ -558,7 +629,7 @@ int rq_apply_circuit(const rq_circuit *circuit, const double *gates, void *d_sta
     fill_pass(a, pp, L);
     a.src_psi = d_states;
     a.dst_psi = d_states;
-    if (launch_pass(L.is_double, L.nt, L.parity, OP_APPLY, ST_FWD, a, grid, s))
+    if (launch_prof(L.is_double, L.nt, L.parity, OP_APPLY, ST_FWD, a, grid, s, 2))
       return fail(RQ_EHIP, "apply pass launch failed");
   }
   return RQ_OK;
@@ -572,6 +643,44 @@ int rq_plan_passes(const rq_circuit *circuit, int32_t op, int32_t dtype, int32_t
     for (size_t p = 0; p < L.plan.size(); ++p)
       for (const GateRef &g : L.plan[p].gates) pass_of[g.inst] = (int32_t)p;
   return (int)L.plan.size();
+}
+
+int rq_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return RQ_OK;
+}
+
+int rq_profile_read(double *ms, int64_t *launches, double *bytes, double *flops) {
+  std::vector<ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recs.swap(g_prof);
+  }
+  for (int i = 0; i < 12; ++i) {
+    if (ms) ms[i] = 0;
+    if (launches) launches[i] = 0;
+    if (bytes) bytes[i] = 0;
+    if (flops) flops[i] = 0;
+  }
+  int st = RQ_OK;
+  for (const ProfRec &r : recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+      st = fail(RQ_EHIP, "event timing failed");
+    if (r.kind >= 0 && r.kind < 12) {
+      if (ms) ms[r.kind] += t;
+      if (launches) launches[r.kind] += 1;
+      if (bytes) bytes[r.kind] += r.bytes;
+      if (flops) flops[r.kind] += r.flops;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (const ProfRec &r : recs) {
+    g_event_pool.push_back(r.a);
+    g_event_pool.push_back(r.b);
+  }
+  return st;
 }
 
 const char *rq_strerror(int status) {

@@ -55,7 +55,8 @@ _lib = None
 
 EXPORTS = ["rq_workspace_bytes", "rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks",
            "rq_hess_workspace_bytes", "rq_apply_circuit", "rq_tr_step", "rq_tr_accept",
-           "rq_tangent_basis", "rq_plan_passes", "rq_strerror", "rq_last_error"]
+           "rq_tangent_basis", "rq_plan_passes", "rq_profile_enable", "rq_profile_read",
+           "rq_strerror", "rq_last_error"]
 
 
 def lib():
@@ -86,10 +87,13 @@ def lib():
                                C.c_double, dp, C.POINTER(C.c_int32), dp]
     L.rq_tangent_basis.argtypes = [C.c_uint32, dp]
     L.rq_plan_passes.argtypes = [C.POINTER(_Circuit), C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    L.rq_profile_enable.argtypes = [C.c_int]
+    L.rq_profile_read.argtypes = [dp, C.POINTER(C.c_int64), dp, dp]
     L.rq_strerror.restype = C.c_char_p
     L.rq_last_error.restype = C.c_char_p
     for name in ["rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks", "rq_apply_circuit",
-                 "rq_tr_step", "rq_tr_accept", "rq_tangent_basis", "rq_plan_passes"]:
+                 "rq_tr_step", "rq_tr_accept", "rq_tangent_basis", "rq_plan_passes",
+                 "rq_profile_enable", "rq_profile_read"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -421,3 +425,28 @@ def build_trotter_target(k: int, gate_list, dtype: int = RQ_C128, parity: bool =
         ref = torch.eye(n, dtype=td, device=device)
         rq_apply_circuit(circ, gates, ref, dtype=dtype, sector=-1)
     return Target(ref, dtype, parity)
+
+
+STAGES = ("fwd", "last", "bwd")
+OPS = ("cost", "grad", "hvp", "apply")
+
+
+def rq_profile_enable(on: bool = True):
+    _check(lib().rq_profile_enable(1 if on else 0), "rq_profile_enable")
+
+
+def rq_profile_read():
+    """Per (op, stage) kernel time (ms), launches, algorithmic bytes, flops
+    since the last read (HIP events on the launch streams)."""
+    ms = np.zeros(12)
+    n = np.zeros(12, dtype=np.int64)
+    by = np.zeros(12)
+    fl = np.zeros(12)
+    _check(lib().rq_profile_read(_dptr(ms), n.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(by),
+                                 _dptr(fl)), "rq_profile_read")
+    out = {}
+    for i in range(12):
+        if n[i]:
+            out[(OPS[i // 3], STAGES[i % 3])] = dict(ms=float(ms[i]), launches=int(n[i]),
+                                                    bytes=float(by[i]), flops=float(fl[i]))
+    return out
