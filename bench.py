@@ -87,6 +87,27 @@ def roofline(prof, key):
                          frac=round(hbm_frac, 4)))
 
 
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of a sweep kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on a copy
+    kernel), or None when the kernel source changed since it was taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "k_pass_hvp_cfg3_c64.txt")
+    src = os.path.join(ROOT, "paper_2506_23775_amd", "csrc", "rq_sweep.h")
+    if not (os.path.exists(prof) and os.path.exists(src)):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(prof):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != sha:
+        return None
+    v = vals.get(f"traffic_bytes_per_launch[{kernel_key}]")
+    return float(v) if v else None
+
+
 def cpu_baseline(prob, ncols=2, budget_s=15.0):
     """The FP64 oracle timed on the host on a bounded sample: f, gradient and
     HVP contributions of `ncols` basis states of sector 0, extrapolated to the
@@ -187,6 +208,8 @@ def main():
     out["hbm_GBps_algorithmic"] = round(tot_bytes / r64["seconds"] / 1e9, 1)
     dom = max(r64["prof"].items(), key=lambda kv: kv[1]["ms"])[0]
     out["roofline"] = roofline(r64["prof"], dom)
+    if args.chunk == 4096:
+        out["roofline"]["traffic"] = measured_traffic(f"{dom[0]}/{dom[1]}")
 
     if tgt128 is not None:
         log("[bench] c128 timed run")
