@@ -16,6 +16,34 @@
 using namespace rqk;
 using cd = std::complex<double>;
 
+namespace rqk {
+struct HessArgs {
+  const void *coef;
+  void *psi;
+  const void *phi;
+  double *slots;
+  int64_t ld;
+  int64_t slab;
+  int32_t ncols, ncg, kq, n_items, nd, nslots, sector, ngates, ne;
+  uint32_t qmask;
+  int32_t pos[8];
+  GateRef gates[kMaxGates];
+};
+int launch_hess_pass(int is_double, int nt, int mode, const HessArgs &a, int grid, void *s);
+int launch_hole(int is_double, const void *src, void *dst, int64_t rows, int64_t ld, int ncols,
+                int nd, int k, int qh, int ql, int parity, int sector, void *s);
+int launch_target_conj(int is_double, const void *ref, int64_t ld_ref, int64_t col0, void *dst,
+                       int64_t rows, int64_t ld, int ncols, void *s);
+int launch_onehot(int is_double, void *dst, int64_t rows, int64_t ld, int64_t col0, int ncols,
+                  void *s);
+int launch_accum_rows(const double *slots, int rows, int nslots, double *acc, void *s);
+int launch_hess_post(int N, int P, int d, const double *hh, const int32_t *inst_off,
+                     const int32_t *inst_list, const int32_t *ppos, const double *gates64,
+                     const double *egrad,
+                     const double *basis, double *hess_holo, double *hess_real, void *s);
+constexpr int kHessSlots = 256;
+}  // namespace rqk
+
 namespace {
 
 thread_local std::string g_err;
@@ -557,9 +585,288 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
   return RQ_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Hessian blocks
+// ---------------------------------------------------------------------------
+struct HessLayout {
+  Layout g;  // gradient sweep (f, egrad, rgrad) in the first part of the workspace
+  int N = 0, P = 0, nd = 0, ne = 0, nt = 0;
+  size_t esize = 0, slab_bytes = 0;
+  int64_t rows = 0, chunk = 0;
+  size_t off_coef = 0, off_coefT = 0, off_g64 = 0, off_basis = 0, off_ioff = 0, off_ilist = 0,
+         off_ppos = 0,
+         upload_end = 0, off_f = 0, off_eg = 0, off_rg = 0, off_hh = 0, off_slots = 0,
+         off_psi = 0, off_phi = 0, off_arr = 0, total = 0;
+};
+
+int make_hess_layout(const rq_circuit *c, int32_t dtype, int64_t chunk, HessLayout &H) {
+  int st = make_layout(c, RQ_OP_GRAD, dtype, chunk, H.g);
+  if (st) return st;
+  const Layout &L = H.g;
+  H.N = c->n_gates;
+  H.P = c->n_params;
+  H.nd = L.parity ? 8 : 16;
+  H.ne = L.parity ? 16 : 32;
+  H.nt = L.kq >= 4 ? 4 : 2;
+  H.esize = L.esize;
+  H.rows = L.rows;
+  H.chunk = chunk;
+  H.slab_bytes = size_t(L.rows) * size_t(chunk) * L.esize;
+  if ((int64_t(1) << (L.kq - H.nt)) * ((chunk + 63) / 64) * H.nd >= (int64_t(1) << 31))
+    return fail(RQ_EINVAL, "problem too large for one Hessian sweep grid (reduce chunk)");
+  size_t o = L.total;
+  H.off_coef = o;
+  o = align256(o + size_t(H.N) * kCoefStride * L.esize);
+  H.off_coefT = o;
+  o = align256(o + size_t(H.N) * kCoefStride * L.esize);
+  H.off_g64 = o;
+  o = align256(o + size_t(H.P) * 32 * sizeof(double));
+  H.off_basis = o;
+  o = align256(o + size_t(16) * 32 * sizeof(double));
+  H.off_ioff = o;
+  o = align256(o + size_t(H.P + 1) * sizeof(int32_t));
+  H.off_ilist = o;
+  o = align256(o + size_t(H.N) * sizeof(int32_t));
+  H.off_ppos = o;
+  o = align256(o + size_t(H.N) * sizeof(int32_t));
+  H.upload_end = o;
+  H.off_f = o;
+  o = align256(o + sizeof(double));
+  H.off_eg = o;
+  o = align256(o + size_t(H.P) * 32 * sizeof(double));
+  H.off_rg = o;
+  o = align256(o + size_t(H.P) * 32 * sizeof(double));
+  H.off_hh = o;
+  o = align256(o + size_t(H.N) * H.N * H.nd * H.ne * sizeof(double));
+  H.off_slots = o;
+  o = align256(o + size_t(H.N) * H.nd * H.ne * kHessSlots * sizeof(double));
+  H.off_psi = o;
+  o = align256(o + size_t(H.N) * H.slab_bytes);
+  H.off_phi = o;
+  o = align256(o + size_t(H.N) * H.slab_bytes);
+  H.off_arr = o;
+  o = align256(o + size_t(H.nd) * H.slab_bytes);
+  H.total = o;
+  return RQ_OK;
+}
+
+int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const rq_range *range,
+             const rq_exec *ex, double *d_f, double *d_egrad, double *d_rgrad, double *d_hh,
+             double *d_hr) {
+  if (!t || !t->ref) return fail(RQ_EINVAL, "target or target->ref is NULL");
+  if (!ex || !ex->workspace) return fail(RQ_EINVAL, "exec or workspace is NULL");
+  if (!gates) return fail(RQ_EINVAL, "gates is NULL");
+  HessLayout H;
+  int st = make_hess_layout(c, t->dtype, ex->chunk, H);
+  if (st) return st;
+  const Layout &L = H.g;
+  if (ex->workspace_bytes < H.total)
+    return fail(RQ_ESPACE, "workspace too small: need " + std::to_string(H.total) + " bytes");
+  if (reinterpret_cast<uintptr_t>(ex->workspace) & 255)
+    return fail(RQ_EINVAL, "workspace must be 256-byte aligned");
+  Range R;
+  st = check_range(c, L, range, R);
+  if (st) return st;
+  char *ws = static_cast<char *>(ex->workspace);
+  hipStream_t s = static_cast<hipStream_t>(ex->stream);
+  double *f_int = reinterpret_cast<double *>(ws + H.off_f);
+  double *eg_int = reinterpret_cast<double *>(ws + H.off_eg);
+  double *rg_int = reinterpret_cast<double *>(ws + H.off_rg);
+  // f, Euclidean and Riemannian gradient (the Weingarten term needs egrad)
+  rq_exec eg{ws, L.total, ex->chunk, ex->stream};
+  st = run_sweep(c, t, gates, nullptr, range, &eg, RQ_OP_GRAD, f_int, eg_int, rg_int, nullptr,
+                 nullptr);
+  if (st) return st;
+
+  // One fused gate order pi for the whole Hessian: the passes of the full
+  // circuit, gates in pass order.  pi is a valid reordering (gates sharing a
+  // qubit keep their order), and every state used below -- psi before each
+  // gate, phi after each gate, the hole arrays -- is propagated along pi, so
+  // each contraction sandwiches consistent sides of the same network.
+  const int N = H.N, P = H.P;
+  std::string err;
+  std::vector<PlanPass> full;
+  if (!plan_passes(c->n_qubits, N, c->pairs, L.parity, H.nt, kMaxGates, full, err))
+    return fail(RQ_EINVAL, err);
+  std::vector<int> order, pass_of(N), pos_in(N), ppos(N);
+  for (size_t i = 0; i < full.size(); ++i)
+    for (size_t j = 0; j < full[i].gates.size(); ++j) {
+      const int g = full[i].gates[j].inst;
+      pass_of[g] = (int)i;
+      pos_in[g] = (int)j;
+      ppos[g] = (int)order.size();
+      order.push_back(g);
+    }
+  std::vector<PlanPass> single(N);
+  for (int g = 0; g < N; ++g) {
+    std::vector<PlanPass> pp;
+    if (!plan_passes(c->n_qubits, 1, c->pairs + 2 * g, L.parity, 2, 1, pp, err) || pp.size() != 1)
+      return fail(RQ_EINVAL, err);
+    single[g] = pp[0];
+    single[g].gates[0].inst = (int16_t)g;
+  }
+
+  // upload: G and G^T coefficients, FP64 gates, tangent basis, instance lists
+  st = prepare_upload(c, L, gates, nullptr);
+  if (st) return st;
+  std::vector<char> hs(H.upload_end - L.total, 0);
+  std::memcpy(hs.data() + (H.off_coef - L.total), g_stage.data() + L.off_coef,
+              size_t(N) * kCoefStride * L.esize);
+  std::memcpy(hs.data() + (H.off_g64 - L.total), g_stage.data() + L.off_g64,
+              size_t(P) * 32 * sizeof(double));
+  for (int l = 0; l < N; ++l) {  // transposed blocks, for phi <- G^T phi
+    cd G[16], Gt[16];
+    load_gate(gates, param_of(c, l), L.parity, G);
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) Gt[4 * i + j] = G[4 * j + i];
+    char *d = hs.data() + (H.off_coefT - L.total) + size_t(l) * kCoefStride * L.esize;
+    if (L.is_double)
+      put_block<double>(d, Gt, L.parity);
+    else
+      put_block<float>(d, Gt, L.parity);
+  }
+  rq_tangent_basis(L.parity ? RQ_PARITY : 0u,
+                   reinterpret_cast<double *>(hs.data() + (H.off_basis - L.total)));
+  {
+    int32_t *ioff = reinterpret_cast<int32_t *>(hs.data() + (H.off_ioff - L.total));
+    int32_t *il = reinterpret_cast<int32_t *>(hs.data() + (H.off_ilist - L.total));
+    int pos = 0;
+    for (int p = 0; p < P; ++p) {
+      ioff[p] = pos;
+      for (int l = 0; l < N; ++l)
+        if (param_of(c, l) == p) il[pos++] = l;
+    }
+    ioff[P] = pos;
+    int32_t *pp = reinterpret_cast<int32_t *>(hs.data() + (H.off_ppos - L.total));
+    for (int l = 0; l < N; ++l) pp[l] = ppos[l];
+  }
+  st = hip_check(hipMemcpyAsync(ws + L.total, hs.data(), hs.size(), hipMemcpyHostToDevice, s),
+                 "upload");
+  if (st) return st;
+  double *hh = reinterpret_cast<double *>(ws + H.off_hh);
+  double *slots = reinterpret_cast<double *>(ws + H.off_slots);
+  if (launch_zero(hh, int64_t(N) * N * H.nd * H.ne, s)) return fail(RQ_EHIP, "zero launch failed");
+  char *psi = ws + H.off_psi;
+  char *phi = ws + H.off_phi;
+  char *arr = ws + H.off_arr;
+  auto slab = [&](char *b, int i) -> char * { return b + size_t(i) * H.slab_bytes; };
+
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.kq = L.kq;
+  a.ld = H.chunk;
+  HessArgs ha;
+  std::memset(&ha, 0, sizeof(ha));
+  ha.coef = ws + H.off_coef;
+  ha.psi = arr;
+  ha.phi = phi;
+  ha.slots = slots;
+  ha.ld = H.chunk;
+  ha.slab = H.rows * H.chunk;
+  ha.kq = L.kq;
+  ha.nd = H.nd;
+  ha.ne = H.ne;
+  ha.nslots = kHessSlots;
+
+  for (int si = 0; si < R.nsec; ++si) {
+    const int sector = R.sectors[si];
+    a.sector = sector;
+    ha.sector = sector;
+    const char *ref = static_cast<const char *>(t->ref) + size_t(sector) * size_t(t->sector_stride) * L.esize;
+    for (int64_t j0 = R.begin; j0 < R.begin + R.count; j0 += H.chunk) {
+      const int ncols = (int)std::min<int64_t>(H.chunk, R.begin + R.count - j0);
+      const int ncg = (ncols + 63) / 64;
+      a.col0 = j0;
+      a.ncols = ncols;
+      a.ncg = ncg;
+      a.n_items = (int)((int64_t(1) << (L.kq - 2)) * ncg);
+      const int grid2 = (int)((std::min<int64_t>(a.n_items, kMaxWaves) + 3) / 4);
+      // psi before every gate along pi (slab t = before the t-th gate of pi)
+      if (launch_onehot(L.is_double, slab(psi, 0), H.rows, H.chunk, j0, ncols, s))
+        return fail(RQ_EHIP, "onehot launch failed");
+      a.coef = ws + H.off_coef;
+      for (int t = 1; t < N; ++t) {
+        fill_pass(a, single[order[t - 1]], L);
+        a.src_psi = slab(psi, t - 1);
+        a.dst_psi = slab(psi, t);
+        if (launch_pass(L.is_double, 2, L.parity, OP_COST, ST_FWD, a, grid2, s))
+          return fail(RQ_EHIP, "forward state launch failed");
+      }
+      // phi at the output side of every gate along pi (slab = instance)
+      if (launch_target_conj(L.is_double, ref, t->ld, j0, slab(phi, order[N - 1]), H.rows, H.chunk,
+                             ncols, s))
+        return fail(RQ_EHIP, "target launch failed");
+      a.coef = ws + H.off_coefT;
+      for (int t = N - 1; t >= 1; --t) {
+        fill_pass(a, single[order[t]], L);
+        a.src_psi = slab(phi, order[t]);
+        a.dst_psi = slab(phi, order[t - 1]);
+        if (launch_pass(L.is_double, 2, L.parity, OP_COST, ST_FWD, a, grid2, s))
+          return fail(RQ_EHIP, "backward state launch failed");
+      }
+      // hole-array sweeps: hole at the t-th gate of pi, then the rest of its
+      // pass and every later pass
+      ha.ncols = ncols;
+      ha.ncg = ncg;
+      ha.n_items = (int)((int64_t(1) << (L.kq - H.nt)) * ncg * H.nd);
+      const int waves = (int)std::min<int64_t>(ha.n_items, kHessSlots);
+      const int gridh = (waves + 3) / 4;
+      const int rows_all = N * H.nd * H.ne;
+      for (int t = 0; t + 1 < N; ++t) {
+        const int h = order[t];
+        const int qh = c->pairs[2 * h], ql = c->pairs[2 * h + 1];
+        if (launch_hole(L.is_double, slab(psi, t), arr, H.rows, H.chunk, ncols, H.nd, c->n_qubits,
+                        qh, ql, L.parity, sector, s))
+          return fail(RQ_EHIP, "hole launch failed");
+        if (launch_zero(slots, int64_t(rows_all) * kHessSlots, s))
+          return fail(RQ_EHIP, "zero launch failed");
+        for (size_t i = pass_of[h]; i < full.size(); ++i) {
+          const PlanPass &pp = full[i];
+          const size_t j0g = i == (size_t)pass_of[h] ? size_t(pos_in[h]) + 1 : 0;
+          if (j0g >= pp.gates.size()) continue;
+          ha.qmask = pp.qmask;
+          for (int b = 0; b < 8; ++b) ha.pos[b] = pp.pos[b];
+          ha.ngates = (int)(pp.gates.size() - j0g);
+          for (int g = 0; g < ha.ngates; ++g) ha.gates[g] = pp.gates[j0g + g];
+          if (launch_hess_pass(L.is_double, H.nt, L.parity, ha, gridh, s))
+            return fail(RQ_EHIP, "Hessian pass launch failed");
+        }
+        if (launch_accum_rows(slots, rows_all, kHessSlots, hh + size_t(h) * N * H.nd * H.ne, s))
+          return fail(RQ_EHIP, "accumulate launch failed");
+      }
+    }
+  }
+  const int32_t *ioff = reinterpret_cast<const int32_t *>(ws + H.off_ioff);
+  const int32_t *il = reinterpret_cast<const int32_t *>(ws + H.off_ilist);
+  const int32_t *ppd = reinterpret_cast<const int32_t *>(ws + H.off_ppos);
+  if (launch_hess_post(N, P, H.nd, hh, ioff, il, ppd, reinterpret_cast<const double *>(ws + H.off_g64),
+                       eg_int, reinterpret_cast<const double *>(ws + H.off_basis), d_hh, d_hr, s))
+    return fail(RQ_EHIP, "Hessian assembly launch failed");
+  if (d_f) st = hip_check(hipMemcpyAsync(d_f, f_int, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+  if (!st && d_egrad)
+    st = hip_check(hipMemcpyAsync(d_egrad, eg_int, size_t(P) * 32 * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+  if (!st && d_rgrad)
+    st = hip_check(hipMemcpyAsync(d_rgrad, rg_int, size_t(P) * 32 * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t rq_hess_workspace_bytes(const rq_circuit *circuit, int32_t dtype, int64_t chunk) {
+  HessLayout H;
+  if (make_hess_layout(circuit, dtype, chunk, H)) return 0;
+  return H.total;
+}
+
+int rq_hess_blocks(const rq_circuit *circuit, const rq_target *target, const double *gates,
+                   const rq_range *range, const rq_exec *exec, double *d_f, double *d_egrad,
+                   double *d_rgrad, double *d_hess_holo, double *d_hess_real) {
+  return run_hess(circuit, target, gates, range, exec, d_f, d_egrad, d_rgrad, d_hess_holo,
+                  d_hess_real);
+}
+
 
 size_t rq_workspace_bytes(const rq_circuit *circuit, int32_t op, int32_t dtype, int64_t chunk) {
   if (op == RQ_OP_HESS) {

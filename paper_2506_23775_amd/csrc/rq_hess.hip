@@ -1,12 +1,443 @@
-// Hessian blocks (implementation follows).
-#include <hip/hip_runtime.h>
+// Hessian blocks (arXiv 2506.23775, Sec. "Efficient gradient and Hessian
+// computation" and Sec. "Gate hole application"):
+//   - the gate hole of G_l applied to psi_{l-1} gives a state array with one
+//     slice per gate entry (a, b) (16 slices; 8 for parity gates, Sec.
+//     "Parity-conserving gate structure"): slice (a,b) holds psi_{l-1} with
+//     the pair bits moved from b to a;
+//   - the array is propagated through G_{l+1}, G_{l+2}, ... like a state;
+//   - at every later gate m the hole of G_m is sandwiched between phi at the
+//     output side of m and the array at its input side, giving the block
+//     d^2 h / dG_l[a,b] dG_m[a',b'].
+// GPU design: the slices are independent slabs; a wavefront owns one slice
+// and 64 basis columns, keeps the 2^NT amplitudes of its tile in registers,
+// and fuses every gate of a sweep pass (contraction, then application).  The
+// phi states at each gate output come from a stored per-gate backward sweep
+// and are shared by the slices (read through the L2).  Contractions use the
+// same FP64 wavefront reduce-scatter and per-wave slots as the gradient.
+#include "rq_sweep.h"
 
-#include "../../include/rq.h"
+#define CV(x) decltype(x)::value
 
-extern "C" int rq_hess_blocks(const rq_circuit *, const rq_target *, const double *,
-                              const rq_range *, const rq_exec *, double *, double *, double *,
-                              double *, double *) {
-  return RQ_EINVAL;
+namespace rqk {
+
+struct HessArgs {
+  const void *coef;
+  void *psi;           // hole-array slices [nd][rows][ld]
+  const void *phi;     // phi at the output side of every gate [N][rows][ld]
+  double *slots;       // [((m * nd + mu) * ne + e) * nslots + wave]
+  int64_t ld;
+  int64_t slab;        // rows * ld (elements)
+  int32_t ncols, ncg, kq, n_items, nd, nslots, sector, ngates, ne;
+  uint32_t qmask;
+  int32_t pos[8];
+  GateRef gates[kMaxGates];
+};
+
+// tp[(a', b')] += phi[a'] psi[b'] over the groups of the gate's qubits.
+template <typename R, int NT, int MODE, int C, int NE, int NA>
+__device__ __forceinline__ void contract_gate(const cx<R> (&ps)[NA], const cx<R> (&ph)[NA],
+                                              R (&tp)[NE]) {
+  using K = Codes<MODE, NT>;
+  if constexpr (K::template valid<C>()) {
+    constexpr int H = K::template h<C>(), L = K::template l<C>();
+    if constexpr (MODE == MODE_DENSE) {
+      for_groups<NT, H, L>([&](auto I0, auto I1, auto I2, auto I3) __attribute__((always_inline)) {
+        constexpr int id[4] = {CV(I0), CV(I1), CV(I2), CV(I3)};
+        static_for<0, 16>([&](auto AB) __attribute__((always_inline)) {
+          constexpr int a = CV(AB) / 4, b = CV(AB) % 4, e = 2 * CV(AB);
+          cacc(tp[e], tp[e + 1], ph[id[a]], ps[id[b]]);
+        });
+      });
+    } else {
+      constexpr int KD = K::template kind<C>(), PI = K::template pi<C>();
+      for_blocks<NT, KD, H, L, PI>([&](auto J0, auto J1, auto C00, auto C01, auto C10,
+                                       auto C11) __attribute__((always_inline)) {
+        constexpr int i0 = CV(J0), i1 = CV(J1);
+        cacc(tp[2 * CV(C00)], tp[2 * CV(C00) + 1], ph[i0], ps[i0]);
+        cacc(tp[2 * CV(C01)], tp[2 * CV(C01) + 1], ph[i0], ps[i1]);
+        cacc(tp[2 * CV(C10)], tp[2 * CV(C10) + 1], ph[i1], ps[i0]);
+        cacc(tp[2 * CV(C11)], tp[2 * CV(C11) + 1], ph[i1], ps[i1]);
+      });
+    }
+  }
 }
 
-extern "C" size_t rq_hess_workspace_bytes(const rq_circuit *, int32_t, int64_t) { return 0; }
+template <typename R, int NT, int MODE>
+__global__ __launch_bounds__(kBlock) void k_hess_pass(const HessArgs A) {
+  constexpr int NA = 1 << NT;
+  constexpr int NE = MODE == MODE_DENSE ? 32 : 16;
+  constexpr int LV = ilog2<NE>();
+  constexpr uint32_t ES = sizeof(cx<R>);
+  using K = Codes<MODE, NT>;
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63;
+  const int wib = threadIdx.x >> 6;
+  const int gwave = blockIdx.x * (kBlock / 64) + wib;
+  const int nwaves = gridDim.x * (kBlock / 64);
+  double *acc = lds + wib * (kMaxGates * NE);
+  const int my_e = entry_of_lane(lane, LV);
+  const bool writer = (lane >> LV) == 0;
+  for (int g = 0; g < A.ngates; ++g)
+    if (writer) acc[g * NE + my_e] = 0.0;
+  ccoef_t<R> *coef = as_const_coef<R>(A.coef);
+  int64_t bstep[NT];
+  static_for<0, NT>([&](auto B) __attribute__((always_inline)) {
+    bstep[CV(B)] = (int64_t(1) << A.pos[CV(B)]) * A.ld * ES;
+  });
+  auto boff = [&](auto I) __attribute__((always_inline)) {
+    int64_t o = 0;
+    static_for<0, NT>([&](auto B) __attribute__((always_inline)) {
+      if constexpr ((CV(I) >> CV(B)) & 1) o += bstep[CV(B)];
+    });
+    return o;
+  };
+  const int mu = gwave % A.nd;  // every item of this wavefront has the same slice
+  for (int item = gwave; item < A.n_items; item += nwaves) {
+    const int rest = item / A.nd;
+    const int cg = rest % A.ncg;
+    const int tile = rest / A.ncg;
+    const int c = cg * 64 + lane;
+    const bool ok = c < A.ncols;
+    const int cc = ok ? c : A.ncols - 1;
+    const uint32_t voff = uint32_t(cc) * ES;
+    int64_t base = 0;
+    {
+      int t = tile;
+      for (int p = 0; p < A.kq; ++p)
+        if (!((A.qmask >> p) & 1)) {
+          base |= int64_t(t & 1) << p;
+          t >>= 1;
+        }
+    }
+    const int pi = MODE == MODE_PARITY ? ((A.sector ^ __builtin_popcountll(base)) & 1) : 0;
+    const int64_t rowb = base * A.ld * ES;
+    const cx<R> zero{R(0), R(0)};
+    char *sl = reinterpret_cast<char *>(A.psi) + int64_t(mu) * A.slab * ES + rowb;
+    cx<R> ps[NA], ph[NA];
+    static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+      const cx<R> v = ldrow<R>(sl + boff(I), voff);
+      ps[CV(I)] = ok ? v : zero;
+    });
+    for (int g = 0; g < A.ngates; ++g) {
+      const GateRef gr = A.gates[g];
+      ccoef_t<R> *co = coef + int64_t(gr.inst) * kCoefStride;
+      const char *pp = reinterpret_cast<const char *>(A.phi) + int64_t(gr.inst) * A.slab * ES + rowb;
+      static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+        const cx<R> v = ldrow<R>(pp + boff(I), voff);
+        ph[CV(I)] = ok ? v : zero;
+      });
+      R tp[NE];
+      static_for<0, NE>([&](auto E) __attribute__((always_inline)) { tp[CV(E)] = R(0); });
+      dispatch<0, K::n>(gate_code(MODE, NT, gr, pi), [&](auto CC) __attribute__((always_inline)) {
+        contract_gate<R, NT, MODE, CV(CC), NE>(ps, ph, tp);
+        fwd_gate<R, NT, MODE, false, CV(CC)>(ps, ps, co);
+      });
+      const double r = wave_reduce_scatter<R, NE>(tp, lane);
+      if (writer) acc[g * NE + my_e] += r;
+    }
+    if (ok)
+      static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+        strow<R>(sl + boff(I), voff, ps[CV(I)]);
+      });
+  }
+  if (writer)
+    for (int g = 0; g < A.ngates; ++g) {
+      double *s = A.slots + ((int64_t(A.gates[g].inst) * A.nd + mu) * A.ne + my_e) * A.nslots + gwave;
+      *s += acc[g * NE + my_e];
+    }
+}
+
+// Hole application: slice mu = (a, b) of the array is psi with the pair bits
+// of the hole gate moved from b to a (zero where the pair bits differ from a).
+template <typename R>
+__global__ void k_hole(const cx<R> *__restrict__ src, cx<R> *__restrict__ dst, int64_t rows,
+                       int64_t ld, int ncols, int nd, int k, int qh, int ql, int parity,
+                       int sector) {
+  const int64_t total = int64_t(nd) * rows * ld;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c = i % ld;
+    const int64_t x = (i / ld) % rows;
+    const int mu = int(i / (ld * rows));
+    int a, b;
+    if (parity) {
+      const int pa[8] = {0, 0, 3, 3, 1, 1, 2, 2}, pb[8] = {0, 3, 0, 3, 1, 2, 1, 2};
+      a = pa[mu];
+      b = pb[mu];
+    } else {
+      a = mu >> 2;
+      b = mu & 3;
+    }
+    int64_t xf = x;
+    if (parity) xf = (x << 1) | ((__builtin_popcountll(x) & 1) ^ sector);
+    const int sh = k - 1 - qh, sl = k - 1 - ql;
+    const int bits = int(((xf >> sh) & 1) << 1 | ((xf >> sl) & 1));
+    cx<R> v{R(0), R(0)};
+    if (bits == a && c < ncols) {
+      int64_t sf = xf & ~((int64_t(1) << sh) | (int64_t(1) << sl));
+      sf |= (int64_t(b >> 1) << sh) | (int64_t(b & 1) << sl);
+      const int64_t sr = parity ? (sf >> 1) : sf;
+      v = src[sr * ld + c];
+    }
+    dst[i] = v;
+  }
+}
+
+// phi at the output side of the last gate: conj(U|j>), zero in padding columns.
+template <typename R>
+__global__ void k_target_conj(const cx<R> *__restrict__ ref, int64_t ld_ref, int64_t col0,
+                              cx<R> *__restrict__ dst, int64_t rows, int64_t ld, int ncols) {
+  const int64_t total = rows * ld;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c = i % ld, x = i / ld;
+    cx<R> v{R(0), R(0)};
+    if (c < ncols) {
+      v = ref[x * ld_ref + col0 + c];
+      v.y = -v.y;
+    }
+    dst[i] = v;
+  }
+}
+
+// |j> for the chunk columns j = col0 + c.
+template <typename R>
+__global__ void k_onehot(cx<R> *__restrict__ dst, int64_t rows, int64_t ld, int64_t col0,
+                         int ncols) {
+  const int64_t total = rows * ld;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c = i % ld, x = i / ld;
+    cx<R> v{R(0), R(0)};
+    if (c < ncols && x == col0 + c) v.x = R(1);
+    dst[i] = v;
+  }
+}
+
+// acc[r] += sum_s slots[r * nslots + s] (fixed-order tree).
+__global__ __launch_bounds__(256) void k_accum_rows(const double *__restrict__ slots, int nslots,
+                                                    double *__restrict__ acc) {
+  __shared__ double red[256];
+  const double *s = slots + int64_t(blockIdx.x) * nslots;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nslots; i += 256) v += s[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[blockIdx.x] += red[0];
+}
+
+// ---------------------------------------------------------------------------
+// FP64 assembly per parameter pair (p, q):
+//   Hh_pq[e][e'] = sum over instance pairs l in p, m in q, l before m of
+//                  hh[l][m][e][e']  +  sum over l in q, m in p, l before m of
+//                  hh[l][m][e'][e]           (d^2 h / dG_p[e] dG_q[e'])
+// where "before" is the position in the fused gate order of the sweeps.
+//   H[(p,r),(q,s)] = -Re sum_{e,e'} X_pr[e] Hh_pq[e][e'] X_qs[e']
+//                    - delta_pq Re Tr[A_r^dagger A_s sym(G_p^dagger egrad_p)]
+// with X_pr = G_p A_r (orthonormal tangent basis) -- the Riemannian Hessian
+// of Sec. "Riemannian optimization" in coordinates; the second term is the
+// Weingarten part of P_G(D egrad[X] - X sym(G^dagger egrad)).
+// hh layout: [l][m][mu][e'] complex with e' the contraction entry at m (16
+// dense, 8 parity) and mu the hole slice at l.
+// ---------------------------------------------------------------------------
+struct zc {
+  double x, y;
+};
+__device__ inline zc zmul(zc a, zc b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+
+__global__ __launch_bounds__(256) void k_hess_post(
+    int N, int P, int d, const double *__restrict__ hh, const int32_t *__restrict__ inst_off,
+    const int32_t *__restrict__ inst_list, const int32_t *__restrict__ ppos,
+    const double *__restrict__ gates64,
+    const double *__restrict__ egrad, const double *__restrict__ basis, double *hess_holo,
+    double *hess_real) {
+  const int p = blockIdx.x / P, q = blockIdx.x % P;
+  __shared__ zc Hh[256], Xp[256], Xq[256];
+  __shared__ zc Sp[16];
+  const int t = threadIdx.x;
+  // entry index e -> row-major 4x4 position
+  const int pidx[8] = {0, 3, 12, 15, 5, 6, 9, 10};
+  auto epos = [&](int e) { return d == 8 ? pidx[e] : e; };
+  if (t < d * d) {
+    const int e = t / d, f = t % d;
+    double sx = 0, sy = 0;
+    for (int i = inst_off[p]; i < inst_off[p + 1]; ++i)
+      for (int j = inst_off[q]; j < inst_off[q + 1]; ++j) {
+        const int l = inst_list[i], m = inst_list[j];
+        if (ppos[l] < ppos[m]) {
+          const double *h = hh + ((int64_t(l) * N + m) * d + e) * 2 * d + 2 * f;
+          sx += h[0];
+          sy += h[1];
+        }
+      }
+    for (int i = inst_off[q]; i < inst_off[q + 1]; ++i)
+      for (int j = inst_off[p]; j < inst_off[p + 1]; ++j) {
+        const int l = inst_list[i], m = inst_list[j];
+        if (ppos[l] < ppos[m]) {
+          const double *h = hh + ((int64_t(l) * N + m) * d + f) * 2 * d + 2 * e;
+          sx += h[0];
+          sy += h[1];
+        }
+      }
+    Hh[t] = {sx, sy};
+    if (hess_holo) {
+      double *o = hess_holo + ((((int64_t(p) * d + e) * P + q) * d + f) * 2);
+      o[0] = sx;
+      o[1] = sy;
+    }
+    // X_p[r][e] = (G_p A_r)[pos(e)], X_q likewise
+    const int r = e, pe = epos(f);
+    const int row = pe / 4, col = pe % 4;
+    zc xp{0, 0}, xq{0, 0};
+    for (int k2 = 0; k2 < 4; ++k2) {
+      const zc a{basis[(r * 16 + k2 * 4 + col) * 2], basis[(r * 16 + k2 * 4 + col) * 2 + 1]};
+      const zc gp{gates64[(p * 16 + row * 4 + k2) * 2], gates64[(p * 16 + row * 4 + k2) * 2 + 1]};
+      const zc gq{gates64[(q * 16 + row * 4 + k2) * 2], gates64[(q * 16 + row * 4 + k2) * 2 + 1]};
+      const zc u = zmul(gp, a), v = zmul(gq, a);
+      xp.x += u.x;
+      xp.y += u.y;
+      xq.x += v.x;
+      xq.y += v.y;
+    }
+    Xp[t] = xp;
+    Xq[t] = xq;
+  }
+  if (t < 16 && p == q) {
+    // S = sym(G^dagger egrad)
+    const int i = t / 4, j = t % 4;
+    zc s1{0, 0}, s2{0, 0};
+    for (int k2 = 0; k2 < 4; ++k2) {
+      const zc gki{gates64[(p * 16 + k2 * 4 + i) * 2], -gates64[(p * 16 + k2 * 4 + i) * 2 + 1]};
+      const zc ekj{egrad[(p * 16 + k2 * 4 + j) * 2], egrad[(p * 16 + k2 * 4 + j) * 2 + 1]};
+      const zc gkj{gates64[(p * 16 + k2 * 4 + j) * 2], -gates64[(p * 16 + k2 * 4 + j) * 2 + 1]};
+      const zc eki{egrad[(p * 16 + k2 * 4 + i) * 2], egrad[(p * 16 + k2 * 4 + i) * 2 + 1]};
+      const zc u = zmul(gki, ekj), v = zmul(gkj, eki);
+      s1.x += u.x;
+      s1.y += u.y;
+      s2.x += v.x;
+      s2.y += v.y;
+    }
+    Sp[t] = {0.5 * (s1.x + s2.x), 0.5 * (s1.y - s2.y)};
+  }
+  __syncthreads();
+  if (t < d * d && hess_real) {
+    const int r = t / d, s = t % d;
+    double acc = 0.0;
+    for (int e = 0; e < d; ++e) {
+      zc inner{0, 0};
+      for (int f = 0; f < d; ++f) {
+        const zc u = zmul(Hh[e * d + f], Xq[s * d + f]);
+        inner.x += u.x;
+        inner.y += u.y;
+      }
+      const zc w = zmul(Xp[r * d + e], inner);
+      acc -= w.x;
+    }
+    if (p == q) {
+      // Re Tr[A_r^dagger A_s S]
+      double tr = 0.0;
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          zc as_s{0, 0};
+          for (int k2 = 0; k2 < 4; ++k2) {
+            const zc a{basis[(s * 16 + i * 4 + k2) * 2], basis[(s * 16 + i * 4 + k2) * 2 + 1]};
+            const zc u = zmul(a, Sp[k2 * 4 + j]);
+            as_s.x += u.x;
+            as_s.y += u.y;
+          }
+          // (A_r^dagger)[j][i] = conj(A_r[i][j]) contributes to trace index j
+          const zc ar{basis[(r * 16 + i * 4 + j) * 2], -basis[(r * 16 + i * 4 + j) * 2 + 1]};
+          tr += zmul(ar, as_s).x;
+        }
+      acc -= tr;
+    }
+    hess_real[(int64_t(p) * d + r) * (int64_t(P) * d) + int64_t(q) * d + s] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+template <typename R, int NT, int MODE>
+static int launch_hess_one(const HessArgs &a, int grid, void *s) {
+  constexpr int NE = MODE == MODE_DENSE ? 32 : 16;
+  const size_t lds = size_t(kBlock / 64) * kMaxGates * NE * sizeof(double);
+  hipLaunchKernelGGL((k_hess_pass<R, NT, MODE>), dim3(grid), dim3(kBlock), lds, (hipStream_t)s,
+                     a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_hess_pass(int is_double, int nt, int mode, const HessArgs &a, int grid, void *s) {
+  if (!is_double) {
+    if (nt == 4) return mode ? launch_hess_one<float, 4, 1>(a, grid, s) : launch_hess_one<float, 4, 0>(a, grid, s);
+    if (nt == 2) return mode ? launch_hess_one<float, 2, 1>(a, grid, s) : launch_hess_one<float, 2, 0>(a, grid, s);
+  } else {
+    if (nt == 4) return mode ? launch_hess_one<double, 4, 1>(a, grid, s) : launch_hess_one<double, 4, 0>(a, grid, s);
+    if (nt == 2) return mode ? launch_hess_one<double, 2, 1>(a, grid, s) : launch_hess_one<double, 2, 0>(a, grid, s);
+  }
+  return -3;
+}
+
+static int grid_of(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+int launch_hole(int is_double, const void *src, void *dst, int64_t rows, int64_t ld, int ncols,
+                int nd, int k, int qh, int ql, int parity, int sector, void *s) {
+  const int g = grid_of(int64_t(nd) * rows * ld);
+  if (is_double)
+    hipLaunchKernelGGL(k_hole<double>, dim3(g), dim3(256), 0, (hipStream_t)s,
+                       (const cx<double> *)src, (cx<double> *)dst, rows, ld, ncols, nd, k, qh, ql,
+                       parity, sector);
+  else
+    hipLaunchKernelGGL(k_hole<float>, dim3(g), dim3(256), 0, (hipStream_t)s,
+                       (const cx<float> *)src, (cx<float> *)dst, rows, ld, ncols, nd, k, qh, ql,
+                       parity, sector);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_target_conj(int is_double, const void *ref, int64_t ld_ref, int64_t col0, void *dst,
+                       int64_t rows, int64_t ld, int ncols, void *s) {
+  const int g = grid_of(rows * ld);
+  if (is_double)
+    hipLaunchKernelGGL(k_target_conj<double>, dim3(g), dim3(256), 0, (hipStream_t)s,
+                       (const cx<double> *)ref, ld_ref, col0, (cx<double> *)dst, rows, ld, ncols);
+  else
+    hipLaunchKernelGGL(k_target_conj<float>, dim3(g), dim3(256), 0, (hipStream_t)s,
+                       (const cx<float> *)ref, ld_ref, col0, (cx<float> *)dst, rows, ld, ncols);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_onehot(int is_double, void *dst, int64_t rows, int64_t ld, int64_t col0, int ncols,
+                  void *s) {
+  const int g = grid_of(rows * ld);
+  if (is_double)
+    hipLaunchKernelGGL(k_onehot<double>, dim3(g), dim3(256), 0, (hipStream_t)s,
+                       (cx<double> *)dst, rows, ld, col0, ncols);
+  else
+    hipLaunchKernelGGL(k_onehot<float>, dim3(g), dim3(256), 0, (hipStream_t)s, (cx<float> *)dst,
+                       rows, ld, col0, ncols);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_accum_rows(const double *slots, int rows, int nslots, double *acc, void *s) {
+  if (rows == 0) return 0;
+  hipLaunchKernelGGL(k_accum_rows, dim3(rows), dim3(256), 0, (hipStream_t)s, slots, nslots, acc);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_hess_post(int N, int P, int d, const double *hh, const int32_t *inst_off,
+                     const int32_t *inst_list, const int32_t *ppos, const double *gates64,
+                     const double *egrad, const double *basis, double *hess_holo,
+                     double *hess_real, void *s) {
+  hipLaunchKernelGGL(k_hess_post, dim3(P * P), dim3(256), 0, (hipStream_t)s, N, P, d, hh,
+                     inst_off, inst_list, ppos, gates64, egrad, basis, hess_holo, hess_real);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace rqk

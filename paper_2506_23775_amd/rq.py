@@ -244,7 +244,10 @@ def default_chunk(circuit: Circuit, op: int, dtype: int, ncols: int,
     top = max(64, 1 << int(np.ceil(np.log2(max(ncols, 64)))))
     chunk = top
     while chunk > 64:
-        need = L.rq_workspace_bytes(C.byref(circuit._c), op, dtype, chunk)
+        if op == RQ_OP_HESS:
+            need = L.rq_hess_workspace_bytes(C.byref(circuit._c), dtype, chunk)
+        else:
+            need = L.rq_workspace_bytes(C.byref(circuit._c), op, dtype, chunk)
         if need and need <= budget_bytes:
             break
         chunk //= 2
