@@ -97,6 +97,8 @@ typedef struct rq_circuit {
  * General mode: ref[x*ld + j] = U[x][j], x, j < 2^k.
  * Parity mode:  ref[s*sector_stride + x'*ld + j'] = U[x][j] for the sector s
  *               blocks (U conserves parity), x', j' < 2^(k-1).
+ * Only the columns of the requested basis range are read, so ref may point
+ * (by offset) into a narrower window of columns.
  * dtype is also the state precision of the evaluation. */
 typedef struct rq_target {
   int32_t dtype;
@@ -121,12 +123,18 @@ typedef struct rq_range {
 /* Execution resources.  workspace: device memory of at least
  * rq_workspace_bytes(circuit, op, dtype, chunk) bytes, 256-byte aligned.
  * chunk: basis columns per sweep (multiple of 64, >= 64).  stream: a
- * hipStream_t (NULL = default stream). */
+ * hipStream_t (NULL = default stream).  flags: RQ_EXEC_ACCUMULATE makes
+ * rq_cost / rq_grad / rq_hvp add their results to the device outputs instead
+ * of overwriting them (all outputs are linear in the basis-state sum, so the
+ * partial sums of disjoint ranges add up to the sum over their union). */
+#define RQ_EXEC_ACCUMULATE 1u
 typedef struct rq_exec {
   void *workspace;
   size_t workspace_bytes;
   int64_t chunk;
   void *stream;
+  uint32_t flags;
+  uint32_t reserved;
 } rq_exec;
 
 /* Bytes of workspace needed for op (RQ_OP_*) with states of dtype and the

@@ -486,7 +486,8 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
   st = check_range(c, L, range, R);
   if (st) return st;
   const int64_t ncol = int64_t(1) << L.kq;
-  if (t->ld < ncol && R.count > 0) return fail(RQ_EINVAL, "target ld smaller than the column count");
+  if (t->ld < 1) return fail(RQ_EINVAL, "target ld must be positive");
+  (void)ncol;
   st = prepare_upload(c, L, gates, dir);
   if (st) return st;
 
@@ -579,8 +580,8 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
   const double *g64 = reinterpret_cast<const double *>(ws + L.off_g64);
   const double *d64 = reinterpret_cast<const double *>(ws + L.off_d64);
   const int32_t *pof = reinterpret_cast<const int32_t *>(ws + L.off_pof);
-  if (launch_post(L.op, L.parity, c->n_params, N, pof, tsum, L.ne, fsum, kMaxWaves, g64, d64, d_f,
-                  d_egrad, d_rgrad, d_ehvp, d_rhvp, s))
+  if (launch_post(L.op, L.parity, (ex->flags & RQ_EXEC_ACCUMULATE) ? 1 : 0, c->n_params, N, pof,
+                  tsum, L.ne, fsum, kMaxWaves, g64, d64, d_f, d_egrad, d_rgrad, d_ehvp, d_rhvp, s))
     return fail(RQ_EHIP, "post-processing launch failed");
   return RQ_OK;
 }
@@ -673,7 +674,7 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
   double *eg_int = reinterpret_cast<double *>(ws + H.off_eg);
   double *rg_int = reinterpret_cast<double *>(ws + H.off_rg);
   // f, Euclidean and Riemannian gradient (the Weingarten term needs egrad)
-  rq_exec eg{ws, L.total, ex->chunk, ex->stream};
+  rq_exec eg{ws, L.total, ex->chunk, ex->stream, 0u, 0u};
   st = run_sweep(c, t, gates, nullptr, range, &eg, RQ_OP_GRAD, f_int, eg_int, rg_int, nullptr,
                  nullptr);
   if (st) return st;

@@ -68,7 +68,7 @@ int launch_pass(int is_double, int nt, int mode, int op, int stage,
 int launch_reduce(const double *slots, int n_inst, int ne, int nslots,
                   double *out, void *stream);
 int launch_zero(double *p, int64_t n, void *stream);
-int launch_post(int op, int parity, int n_params, int n_inst, const int32_t *param_of,
+int launch_post(int op, int parity, int accumulate, int n_params, int n_inst, const int32_t *param_of,
                 const double *tsum, int ne, const double *fslots, int nslots,
                 const double *gates64, const double *dir64, double *d_f,
                 double *d_egrad, double *d_rgrad, double *d_ehvp, double *d_rhvp,

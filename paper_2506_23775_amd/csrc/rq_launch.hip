@@ -123,25 +123,26 @@ __device__ inline void unpack_T(const double *t, int parity, c64d *M) {
   }
 }
 
-__device__ inline void store4(double *dst, const c64d *M, int parity) {
+__device__ inline void store4(double *dst, const c64d *M, int parity, int accumulate) {
   for (int e = 0; e < 16; ++e) {
     bool keep = true;
     if (parity) {
       keep = false;
       for (int c = 0; c < 8; ++c) keep |= (kParityIdx[c] == e);
     }
-    dst[2 * e] = keep ? M[e].x : 0.0;
-    dst[2 * e + 1] = keep ? M[e].y : 0.0;
+    const double re = keep ? M[e].x : 0.0, im = keep ? M[e].y : 0.0;
+    dst[2 * e] = accumulate ? dst[2 * e] + re : re;
+    dst[2 * e + 1] = accumulate ? dst[2 * e + 1] + im : im;
   }
 }
 
-__global__ void k_post(int op, int parity, int P, int N, const int32_t *__restrict__ param_of,
+__global__ void k_post(int op, int parity, int accumulate, int P, int N, const int32_t *__restrict__ param_of,
                        const double *__restrict__ tsum, int ne, const double *__restrict__ fsum,
                        const double *__restrict__ gates64, const double *__restrict__ dir64,
                        double *d_f, double *d_egrad, double *d_rgrad, double *d_ehvp,
                        double *d_rhvp) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0 && d_f) d_f[0] = -fsum[0];
+  if (p == 0 && d_f) d_f[0] = accumulate ? d_f[0] - fsum[0] : -fsum[0];
   if (p >= P || op == OP_COST) return;
   const int nt1 = parity ? 16 : 32;
   double t[32], td[32];
@@ -160,8 +161,8 @@ __global__ void k_post(int op, int parity, int P, int N, const int32_t *__restri
     eg[e] = {-T[e].x, T[e].y};  // -conj(T)
   }
   proj4(G, eg, rg);
-  if (d_egrad) store4(d_egrad + int64_t(p) * 32, eg, parity);
-  if (d_rgrad) store4(d_rgrad + int64_t(p) * 32, rg, parity);
+  if (d_egrad) store4(d_egrad + int64_t(p) * 32, eg, parity, accumulate);
+  if (d_rgrad) store4(d_rgrad + int64_t(p) * 32, rg, parity, accumulate);
   if (op != OP_HVP) return;
   c64d Td[16], eh[16], X[16], Gd[16], S[16], sym[16], XS[16], Y[16], rh[16];
   unpack_T(td, parity, Td);
@@ -179,17 +180,17 @@ __global__ void k_post(int op, int parity, int P, int N, const int32_t *__restri
   mm4(X, sym, XS);
   for (int e = 0; e < 16; ++e) Y[e] = csub(eh[e], XS[e]);
   proj4(G, Y, rh);
-  if (d_ehvp) store4(d_ehvp + int64_t(p) * 32, eh, parity);
-  if (d_rhvp) store4(d_rhvp + int64_t(p) * 32, rh, parity);
+  if (d_ehvp) store4(d_ehvp + int64_t(p) * 32, eh, parity, accumulate);
+  if (d_rhvp) store4(d_rhvp + int64_t(p) * 32, rh, parity, accumulate);
 }
 
-int launch_post(int op, int parity, int n_params, int n_inst, const int32_t *param_of,
+int launch_post(int op, int parity, int accumulate, int n_params, int n_inst, const int32_t *param_of,
                 const double *tsum, int ne, const double *fsum, int, const double *gates64,
                 const double *dir64, double *d_f, double *d_egrad, double *d_rgrad,
                 double *d_ehvp, double *d_rhvp, void *s) {
   const int threads = 64;
   const int blocks = (n_params + threads - 1) / threads > 0 ? (n_params + threads - 1) / threads : 1;
-  hipLaunchKernelGGL(k_post, dim3(blocks), dim3(threads), 0, (hipStream_t)s, op, parity, n_params,
+  hipLaunchKernelGGL(k_post, dim3(blocks), dim3(threads), 0, (hipStream_t)s, op, parity, accumulate, n_params,
                      n_inst, param_of, tsum, ne, fsum, gates64, dir64, d_f, d_egrad, d_rgrad,
                      d_ehvp, d_rhvp);
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -48,7 +48,10 @@ class _Range(C.Structure):
 
 class _Exec(C.Structure):
     _fields_ = [("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("chunk", C.c_int64), ("stream", C.c_void_p)]
+                ("chunk", C.c_int64), ("stream", C.c_void_p), ("flags", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+RQ_EXEC_ACCUMULATE = 1
 
 
 _lib = None
@@ -186,6 +189,7 @@ class Target:
     ref: torch.Tensor
     dtype: int
     parity: bool
+    col_offset: int = 0     # ref holds the columns [col_offset, col_offset + width)
 
     def struct(self):
         if self.parity:
@@ -194,7 +198,10 @@ class Target:
         else:
             ld = self.ref.shape[1]
             ss = 0
-        return _Target(self.dtype, 0, self.ref.data_ptr(), ld, ss)
+        esize = self.ref.element_size()
+        # the C ABI addresses column j at ref + x*ld + j: shift the base so that
+        # a window of columns starting at col_offset is addressed by global j
+        return _Target(self.dtype, 0, self.ref.data_ptr() - self.col_offset * esize, ld, ss)
 
     @staticmethod
     def from_dense(U: np.ndarray, dtype: int = RQ_C128, parity: bool = False, device="cuda"):
@@ -254,7 +261,7 @@ def default_chunk(circuit: Circuit, op: int, dtype: int, ncols: int,
     return chunk
 
 
-def _exec(circuit: Circuit, op: int, dtype: int, chunk, workspace, stream):
+def _exec(circuit: Circuit, op: int, dtype: int, chunk, workspace, stream, flags=0):
     L = lib()
     if chunk is None:
         chunk = default_chunk(circuit, op, dtype, circuit.ncols)
@@ -268,7 +275,7 @@ def _exec(circuit: Circuit, op: int, dtype: int, chunk, workspace, stream):
     if ws.nbytes < need:
         raise RuntimeError(f"workspace too small: {ws.nbytes} < {need}")
     s = stream if stream is not None else torch.cuda.current_stream()
-    return _Exec(ws.ptr, ws.nbytes, chunk, s.cuda_stream), ws
+    return _Exec(ws.ptr, ws.nbytes, chunk, s.cuda_stream, flags, 0), ws
 
 
 def _range(rng):
@@ -296,11 +303,23 @@ def _cplx(t):
 # Entry points (same names as the C ABI)
 # ---------------------------------------------------------------------------
 
+def _outputs(out, n, P):
+    """Caller-provided float64 device outputs (f [1], then [P,4,4,2] arrays)
+    or fresh zero tensors."""
+    if out is not None:
+        assert len(out) == n
+        return list(out)
+    return [_out((1,))] + [_out((P, 4, 4, 2)) for _ in range(n - 1)]
+
+
 def rq_cost(circuit: Circuit, target: Target, gates, range=None, chunk=None, workspace=None,
-            stream=None) -> torch.Tensor:
+            stream=None, out=None, accumulate=False) -> torch.Tensor:
+    """f over the basis range (device float64 scalar).  With ``out`` (a
+    1-element float64 device tensor) and ``accumulate``, f is added to it."""
     g = _gates_host(gates)
-    ex, ws = _exec(circuit, RQ_OP_COST, target.dtype, chunk, workspace, stream)
-    f = _out((1,))
+    ex, ws = _exec(circuit, RQ_OP_COST, target.dtype, chunk, workspace, stream,
+                   RQ_EXEC_ACCUMULATE if accumulate else 0)
+    (f,) = _outputs(None if out is None else (out,), 1, circuit.n_params)
     t = target.struct()
     _check(lib().rq_cost(C.byref(circuit._c), C.byref(t), _dptr(g), _range(range), C.byref(ex),
                          _ptr(f)), "rq_cost")
@@ -308,12 +327,14 @@ def rq_cost(circuit: Circuit, target: Target, gates, range=None, chunk=None, wor
 
 
 def rq_grad(circuit: Circuit, target: Target, gates, range=None, chunk=None, workspace=None,
-            stream=None):
-    """Returns (f, egrad [P,4,4] complex, rgrad [P,4,4] complex) on the device."""
+            stream=None, out=None, accumulate=False):
+    """Returns (f, egrad [P,4,4] complex, rgrad [P,4,4] complex) on the device.
+    ``out``: (f [1], egrad [P,4,4,2], rgrad [P,4,4,2]) float64 device tensors
+    to write (or, with ``accumulate``, to add) the results into."""
     g = _gates_host(gates)
-    ex, ws = _exec(circuit, RQ_OP_GRAD, target.dtype, chunk, workspace, stream)
-    P = circuit.n_params
-    f, eg, rg = _out((1,)), _out((P, 4, 4, 2)), _out((P, 4, 4, 2))
+    ex, ws = _exec(circuit, RQ_OP_GRAD, target.dtype, chunk, workspace, stream,
+                   RQ_EXEC_ACCUMULATE if accumulate else 0)
+    f, eg, rg = _outputs(out, 3, circuit.n_params)
     t = target.struct()
     _check(lib().rq_grad(C.byref(circuit._c), C.byref(t), _dptr(g), _range(range), C.byref(ex),
                          _ptr(f), _ptr(eg), _ptr(rg)), "rq_grad")
@@ -321,14 +342,14 @@ def rq_grad(circuit: Circuit, target: Target, gates, range=None, chunk=None, wor
 
 
 def rq_hvp(circuit: Circuit, target: Target, gates, direction, range=None, chunk=None,
-           workspace=None, stream=None):
-    """Returns (f, egrad, rgrad, ehvp, rhvp) on the device."""
+           workspace=None, stream=None, out=None, accumulate=False):
+    """Returns (f, egrad, rgrad, ehvp, rhvp) on the device (see rq_grad for
+    ``out`` / ``accumulate``; here five tensors)."""
     g = _gates_host(gates)
     d = _gates_host(direction)
-    ex, ws = _exec(circuit, RQ_OP_HVP, target.dtype, chunk, workspace, stream)
-    P = circuit.n_params
-    f = _out((1,))
-    eg, rg, eh, rh = (_out((P, 4, 4, 2)) for _ in (0, 1, 2, 3))
+    ex, ws = _exec(circuit, RQ_OP_HVP, target.dtype, chunk, workspace, stream,
+                   RQ_EXEC_ACCUMULATE if accumulate else 0)
+    f, eg, rg, eh, rh = _outputs(out, 5, circuit.n_params)
     t = target.struct()
     _check(lib().rq_hvp(C.byref(circuit._c), C.byref(t), _dptr(g), _dptr(d), _range(range),
                         C.byref(ex), _ptr(f), _ptr(eg), _ptr(rg), _ptr(eh), _ptr(rh)), "rq_hvp")
@@ -453,3 +474,18 @@ def rq_profile_read():
             out[(OPS[i // 3], STAGES[i % 3])] = dict(ms=float(ms[i]), launches=int(n[i]),
                                                     bytes=float(by[i]), flops=float(fl[i]))
     return out
+
+
+def build_target_window(k: int, gate_list, j0: int, n: int, dtype: int = RQ_C128,
+                        device="cuda") -> Target:
+    """Columns U|j>, j0 <= j < j0 + n, of the target given by a gate list
+    (general mode), built on the device with rq_apply_circuit.  Use with a
+    basis range inside the window."""
+    pairs = [p for p, _ in gate_list]
+    gates = np.stack([G for _, G in gate_list])
+    circ = Circuit(k, pairs)
+    ref = torch.zeros((1 << k, n), dtype=torch_dtype(dtype), device=device)
+    idx = torch.arange(n, device=device)
+    ref[j0 + idx, idx] = 1.0
+    rq_apply_circuit(circ, gates, ref, dtype=dtype, sector=-1)
+    return Target(ref, dtype, False, col_offset=j0)
