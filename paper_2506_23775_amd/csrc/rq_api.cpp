@@ -413,12 +413,19 @@ void fill_pass(PassArgs &a, const PlanPass &pp, const Layout &L) {
   for (int g = 0; g < a.ngates; ++g) a.gates[g] = pp.gates[g];
 }
 
-int grid_for(const Layout &L, int ncols, int &items, int &ncg) {
+// Blocks of 4 wavefronts for a sweep over ncols columns.  Passes that
+// accumulate partial sums own one FP64 slot per wavefront (at most
+// kMaxWaves); plain forward passes accumulate nothing and may use up to
+// kFwdWaves wavefronts (8 per SIMD) to hide memory latency.
+constexpr int64_t kFwdWaves = 4 * int64_t(kMaxWaves);
+
+int grid_for(const Layout &L, int ncols, int &items, int &ncg, bool fwd = false) {
   ncg = (ncols + 63) / 64;
   const int64_t tiles = int64_t(1) << (L.kq - L.nt);
   const int64_t it = tiles * ncg;
   items = (int)it;
-  const int64_t waves = it < kMaxWaves ? it : kMaxWaves;
+  const int64_t cap = fwd ? kFwdWaves : kMaxWaves;
+  const int64_t waves = it < cap ? it : cap;
   return (int)((waves + 3) / 4);
 }
 
@@ -528,6 +535,7 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
       const int ncols = (int)std::min<int64_t>(L.chunk, R.begin + R.count - j0);
       int items, ncg;
       const int grid = grid_for(L, ncols, items, ncg);
+      const int grid_fwd = grid_for(L, ncols, items, ncg, true);
       a.col0 = j0;
       a.ncols = ncols;
       a.ncg = ncg;
@@ -544,7 +552,7 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
           a.dst_psi = buf(nst * p);
           a.dst_dpsi = nst == 2 ? buf(nst * p + 1) : nullptr;
         }
-        if (launch_prof(L.is_double, L.nt, L.parity, L.op, ST_FWD, a, grid, s,
+        if (launch_prof(L.is_double, L.nt, L.parity, L.op, ST_FWD, a, grid_fwd, s,
                         (p > 0 ? nst : 0) + nst))
           return fail(RQ_EHIP, "forward pass launch failed");
       }
@@ -930,7 +938,7 @@ int rq_apply_circuit(const rq_circuit *circuit, const double *gates, void *d_sta
   a.sector = L.parity ? sector : 0;
   a.ncols = (int)n_states;
   int items, ncg;
-  const int grid = grid_for(L, (int)n_states, items, ncg);
+  const int grid = grid_for(L, (int)n_states, items, ncg, true);
   a.ncg = ncg;
   a.n_items = items;
   for (const PlanPass &pp : L.plan) {

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_hess_pass(const HessArgs A) {
   const int nwaves = gridDim.x * (kBlock / 64);
   double *acc = lds + wib * (kMaxGates * NE);
   const int my_e = entry_of_lane(lane, LV);
-  const bool writer = (lane >> LV) == 0;
+  const bool writer = entry_writer(lane, LV);
   for (int g = 0; g < A.ngates; ++g)
     if (writer) acc[g * NE + my_e] = 0.0;
   ccoef_t<R> *coef = as_const_coef<R>(A.coef);

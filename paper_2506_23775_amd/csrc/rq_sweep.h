@@ -118,6 +118,31 @@ __device__ __forceinline__ void strow(char *row, uint32_t voff, cx<R> v) {
   *reinterpret_cast<cx<R> *>(row + voff) = v;
 }
 
+// Direct global->LDS loads (gfx950): each lane of the wavefront writes its
+// `size` bytes at lds + lane * size.  Used to prefetch the next tile of the
+// backward sweep while the current one is computed from registers.  The
+// compiler does not order these against later LDS reads, so the kernel waits
+// on vmcnt explicitly (see k_pass).
+template <int SIZE>
+__device__ __forceinline__ void lds_dma(const char *g, void *lds) {
+  if constexpr (SIZE == 4)
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)g,
+                                     (__attribute__((address_space(3))) void *)lds, 4, 0, 0);
+  else
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)g,
+                                     (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
+
+// s_waitcnt vmcnt(N) with the other counters unconstrained (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+__device__ __forceinline__ void wait_lgkm0() {
+  __builtin_amdgcn_s_waitcnt(0xF | (0x3 << 14) | (0x7 << 4) | (0x0 << 8));
+}
+
 // ----------------------------------------------------------------------------
 // Compile-time iteration over the amplitude groups a gate couples.
 // ----------------------------------------------------------------------------
@@ -420,54 +445,130 @@ __device__ __forceinline__ void bwd_gate(cx<R> (&ps)[NA], cx<R> (&dps)[NA], cx<R
 }
 
 // ----------------------------------------------------------------------------
-// FP64 wavefront reduce-scatter of V per-lane values.  After the call, lane L
-// (with bits >= log2(V) clear) holds the wavefront sum of entry e(L), where
-// e(L) reverses the low log2(V) bits of L.
+// Wavefront reduce-scatter of V = 2^LV per-lane values (LV <= 6).  Step s
+// pairs every lane with a partner that differs in lane bit d_s = 5 - s; the
+// lane with d_s = 0 keeps the lower half of its values plus the partner's
+// lower half, the other the upper halves.  After LV halving steps lane L
+// holds the sum of entry L >> (6 - LV) over the lanes that share its bits
+// 5 .. 6-LV; the remaining steps add over the low bits, so every lane ends
+// with the full wavefront sum of its entry.
+//   s = 0: v_permlane32_swap (lanes L, L^32), s = 1: v_permlane16_swap
+//   (L, L^16): both exchange whole register halves, so the kept/sent halves
+//   need no per-lane select; then DPP inside rows of 16 lanes: row_ror:8
+//   (L^8), row_half_mirror (L^7), quad_perm (L^2), quad_perm (L^1).  The
+//   masks 32, 16, 8, 7, 2, 1 are linearly independent over GF(2) and none
+//   touches an earlier step's bit, so each lane's sum covers all 64 lanes
+//   once.
+// Complex64 states: the two permlane steps add in FP32 (four lanes' partial
+// sums), everything after in FP64.
 // ----------------------------------------------------------------------------
 template <int V>
 __device__ __forceinline__ constexpr int ilog2() {
   return V <= 1 ? 0 : 1 + ilog2<V / 2>();
 }
 
-__device__ __forceinline__ int entry_of_lane(int lane, int lv) {
-  int e = 0;
-  for (int s = 0; s < lv; ++s) e |= ((lane >> s) & 1) << (lv - 1 - s);
-  return e;
+__device__ __forceinline__ int entry_of_lane(int lane, int lv) { return lane >> (6 - lv); }
+__device__ __forceinline__ bool entry_writer(int lane, int lv) {
+  return (lane & ((1 << (6 - lv)) - 1)) == 0;
 }
 
-template <int S, int LV, int V>
-__device__ __forceinline__ void rs_steps(double (&v)[V / 2], int lane) {
-  if constexpr (S < LV) {
-    constexpr int n = V >> S;
-    const bool hi = (lane >> S) & 1;
-    static_for<0, n / 2>([&](auto I) __attribute__((always_inline)) {
-      constexpr int i = CV(I);
-      const double a = v[i], b = v[i + n / 2];
-      const double keep = hi ? b : a, send = hi ? a : b;
-      v[i] = keep + __shfl_xor(send, 1 << S, 64);
-    });
-    rs_steps<S + 1, LV, V>(v, lane);
+// (a, b) -> (a', b') with a' = [a.lo32, b.lo32], b' = [a.hi32, b.hi32] over
+// lane halves (S = 32) or a' = [a.r0, b.r0, a.r2, b.r2],
+// b' = [a.r1, b.r1, a.r3, b.r3] over rows of 16 lanes (S = 16).
+template <int S>
+__device__ __forceinline__ void lane_swap(uint32_t &a, uint32_t &b) {
+  if constexpr (S == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  }
+}
+template <int S>
+__device__ __forceinline__ void lane_swap(float &a, float &b) {
+  uint32_t x = __builtin_bit_cast(uint32_t, a), y = __builtin_bit_cast(uint32_t, b);
+  lane_swap<S>(x, y);
+  a = __builtin_bit_cast(float, x);
+  b = __builtin_bit_cast(float, y);
+}
+template <int S>
+__device__ __forceinline__ void lane_swap(double &a, double &b) {
+  uint64_t x = __builtin_bit_cast(uint64_t, a), y = __builtin_bit_cast(uint64_t, b);
+  uint32_t xl = uint32_t(x), xh = uint32_t(x >> 32), yl = uint32_t(y), yh = uint32_t(y >> 32);
+  lane_swap<S>(xl, yl);
+  lane_swap<S>(xh, yh);
+  a = __builtin_bit_cast(double, uint64_t(xl) | (uint64_t(xh) << 32));
+  b = __builtin_bit_cast(double, uint64_t(yl) | (uint64_t(yh) << 32));
+}
+
+// value of the partner lane inside a row of 16 lanes (DPP control CTRL)
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double v) {
+  const uint64_t x = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_update_dpp(0u, uint32_t(x), CTRL, 0xF, 0xF, false);
+  const uint32_t hi = __builtin_amdgcn_update_dpp(0u, uint32_t(x >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, uint64_t(lo) | (uint64_t(hi) << 32));
+}
+constexpr int kDppRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
+template <int S>
+struct DppStep;  // steps 2..5
+template <> struct DppStep<2> { static constexpr int ctrl = kDppRor8, bit = 3; };
+template <> struct DppStep<3> { static constexpr int ctrl = kDppHalfMirror, bit = 2; };
+template <> struct DppStep<4> { static constexpr int ctrl = kDppXor2, bit = 1; };
+template <> struct DppStep<5> { static constexpr int ctrl = kDppXor1, bit = 0; };
+
+// permlane halving step on n values of type T: v[i] (+) v[i + n/2]
+template <int S, int N, typename T>
+__device__ __forceinline__ void perm_halve(T (&v)[N]) {
+  static_for<0, N / 2>([&](auto I) __attribute__((always_inline)) {
+    constexpr int i = CV(I);
+    T a = v[i], b = v[i + N / 2];
+    lane_swap<S>(a, b);
+    v[i] = a + b;
+  });
+}
+
+// DPP steps STEP.. on the FP64 values (N = values left)
+template <int STEP, int N>
+__device__ __forceinline__ double dpp_steps(double (&v)[N], int lane) {
+  if constexpr (STEP == 6) {
+    return v[0];
+  } else {
+    using D = DppStep<STEP>;
+    if constexpr (N > 1) {
+      const bool hi = (lane >> D::bit) & 1;
+      double w[N / 2];
+      static_for<0, N / 2>([&](auto I) __attribute__((always_inline)) {
+        constexpr int i = CV(I);
+        const double a = v[i], b = v[i + N / 2];
+        const double keep = hi ? b : a, send = hi ? a : b;
+        w[i] = keep + dpp_partner<D::ctrl>(send);
+      });
+      return dpp_steps<STEP + 1, N / 2>(w, lane);
+    } else {
+      double w[1] = {v[0] + dpp_partner<D::ctrl>(v[0])};
+      return dpp_steps<STEP + 1, 1>(w, lane);
+    }
   }
 }
 
 template <typename R, int V>
 __device__ __forceinline__ double wave_reduce_scatter(const R (&tp)[V], int lane) {
-  constexpr int LV = ilog2<V>();
-  double v[V / 2];
-  {
-    const bool hi = lane & 1;
-    static_for<0, V / 2>([&](auto I) __attribute__((always_inline)) {
-      constexpr int i = CV(I);
-      const double a = (double)tp[i], b = (double)tp[i + V / 2];
-      const double keep = hi ? b : a, send = hi ? a : b;
-      v[i] = keep + __shfl_xor(send, 1, 64);
-    });
-  }
-  rs_steps<1, LV, V>(v, lane);
-  double r = v[0];
-#pragma unroll
-  for (int s = LV; s < 6; ++s) r += __shfl_xor(r, 1 << s, 64);
-  return r;
+  static_assert(V >= 4 && V <= 64, "reduce-scatter of 4..64 values");
+  R v0[V];
+  static_for<0, V>([&](auto I) __attribute__((always_inline)) { v0[CV(I)] = tp[CV(I)]; });
+  perm_halve<32, V>(v0);
+  R v1[V / 2];
+  static_for<0, V / 2>([&](auto I) __attribute__((always_inline)) { v1[CV(I)] = v0[CV(I)]; });
+  perm_halve<16, V / 2>(v1);
+  double v2[V / 4];
+  static_for<0, V / 4>([&](auto I) __attribute__((always_inline)) {
+    v2[CV(I)] = (double)v1[CV(I)];
+  });
+  return dpp_steps<2, V / 4>(v2, lane);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -482,6 +583,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Target wavefronts per SIMD of a sweep instantiation: 512 registers per lane
 // divided by the live tile states, the contraction accumulators and a fixed
 // allowance for addresses, coefficients in flight and temporaries.
+// Slabs of a backward tile prefetched into LDS (bit s: 0 checkpoint psi,
+// 1 phi, 2 checkpoint dpsi, 3 dphi).  Complex64 prefetches only the
+// checkpoints: 16 KB of LDS per wavefront at 16 amplitudes leave room for two
+// wavefronts per SIMD.
+template <typename R, int NT, int OP>
+struct Prefetch {
+  static constexpr int mask = sizeof(R) == 4 ? (OP == OP_HVP ? 0x5 : 0x1)
+                                             : (OP == OP_HVP ? 0xf : 0x3);
+};
+
 template <typename R, int NT, int MODE, int OP, int STAGE>
 struct Occupancy {
   static constexpr int words = sizeof(R) / 4;
@@ -511,13 +622,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((
   using K = Codes<MODE, NT>;
   extern __shared__ double lds[];
 
+  // Backward passes run one wavefront per block and prefetch slabs of the
+  // next tile into LDS with direct loads (slab s in PFMASK: 0 checkpoint
+  // psi, 1 phi, 2 checkpoint dpsi, 3 dphi); the others are loaded into
+  // registers at the top of the tile.
+  constexpr bool PF = STAGE == ST_BWD;
+  constexpr int DW = int(ES) / 4;                 // dwords per amplitude
+  constexpr int PFMASK = Prefetch<R, NT, OP>::mask;
+  constexpr int NPF = __builtin_popcount(PFMASK);
+  constexpr int PF_BYTES = PF ? NPF * NA * 64 * int(ES) : 0;
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
-  const int gwave = blockIdx.x * (kBlock / 64) + wib;
-  const int nwaves = gridDim.x * (kBlock / 64);
-  double *acc = lds + wib * (kMaxGates * NE);
+  const int wpb = blockDim.x >> 6;
+  const int gwave = blockIdx.x * wpb + wib;
+  const int nwaves = gridDim.x * wpb;
+  char *pf = reinterpret_cast<char *>(lds);       // PF: this wavefront's tile buffer
+  double *acc = reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + PF_BYTES) +
+                wib * (kMaxGates * NE);
   const int my_e = entry_of_lane(lane, LV);
-  const bool writer = (lane >> LV) == 0;
+  const bool writer = entry_writer(lane, LV);
   if constexpr (NEEDB) {
     for (int g = 0; g < A.ngates; ++g)
       if (writer) acc[g * NE + my_e] = 0.0;
@@ -553,6 +676,70 @@ __global__ __launch_bounds__(kBlock) __attribute__((
     });
     return o;
   };
+
+  // LDS-DMA prefetch of one tile of the backward sweep
+  auto prefetch = [&](int it) __attribute__((always_inline)) {
+    const int pcg = it % A.ncg;
+    const int ptile = it / A.ncg;
+    const int pc = pcg * 64 + lane;
+    const int pcc = pc < A.ncols ? pc : A.ncols - 1;
+    int64_t pbase = 0;
+    {
+      int t = ptile;
+      for (int p = 0; p < A.kq; ++p)
+        if (!((A.qmask >> p) & 1)) {
+          pbase |= int64_t(t & 1) << p;
+          t >>= 1;
+        }
+    }
+    const int64_t prow = pbase * A.ld * ES;
+    const uint32_t pvoff = uint32_t(pcc) * ES;
+    const char *src[4] = {reinterpret_cast<const char *>(A.ckpt_psi),
+                          reinterpret_cast<const char *>(A.phi),
+                          reinterpret_cast<const char *>(A.ckpt_dpsi),
+                          reinterpret_cast<const char *>(A.dphi)};
+    static_for<0, 4>([&](auto S) __attribute__((always_inline)) {
+      constexpr int sl = CV(S);
+      if constexpr ((PFMASK >> sl) & 1) {
+        constexpr int li = __builtin_popcount(PFMASK & ((1 << sl) - 1));
+        if constexpr (DW == 2) {
+          // complex64: 16 bytes per lane = two columns; lanes 0-31 fetch row
+          // I, lanes 32-63 row I+1 of the 64-column segment, so each 16-byte
+          // load lands in LDS in the natural [row][column] order (512 bytes
+          // per row).  ld is a multiple of 64: whole segments are in bounds.
+          const uint32_t hoff = uint32_t(lane & 31) * 16;
+          const int64_t colb = int64_t(pcg) * 64 * ES;
+          static_for<0, NA / 2>([&](auto I2) __attribute__((always_inline)) {
+            constexpr int i0 = 2 * CV(I2);
+            const int64_t rb = (lane < 32) ? boff(ic<i0>{}) : boff(ic<i0 + 1>{});
+            const char *g = src[sl] + prow + rb + colb + hoff;
+            lds_dma<16>(g, pf + (li * NA + i0) * 64 * int(ES));
+          });
+        } else {
+          static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+            const char *g = src[sl] + prow + boff(I) + pvoff;
+            lds_dma<16>(g, pf + (li * NA + CV(I)) * 64 * int(ES));
+          });
+        }
+      }
+    });
+  };
+  // tile -> registers: row I of slab S from LDS ([slab][row][column]) if it
+  // was prefetched, else straight from the slab
+  auto pf_read = [&](auto S, auto I, int64_t rowb, uint32_t voff) __attribute__((always_inline)) {
+    constexpr int sl = CV(S);
+    if constexpr ((PFMASK >> sl) & 1) {
+      constexpr int li = __builtin_popcount(PFMASK & ((1 << sl) - 1));
+      const char *l = pf + (li * NA + CV(I)) * 64 * int(ES);
+      return reinterpret_cast<const cx<R> *>(l)[lane];
+    } else {
+      const void *base = sl == 0 ? A.ckpt_psi : sl == 1 ? A.phi : sl == 2 ? A.ckpt_dpsi : A.dphi;
+      return ldrow<R>(reinterpret_cast<const char *>(base) + rowb + boff(I), voff);
+    }
+  };
+  if constexpr (PF) {
+    if (gwave < A.n_items) prefetch(gwave);
+  }
 
   for (int item = gwave; item < A.n_items; item += nwaves) {
     const int cg = item % A.ncg;
@@ -622,18 +809,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((
         }
       }
     } else {
-      const char *s = reinterpret_cast<const char *>(A.ckpt_psi) + rowb;
+      // Wait for this tile's prefetch.  Only the previous tile's phi stores
+      // (nst * NA vector-memory instructions) were issued after it, so they
+      // may stay outstanding.
+      if (item != gwave && A.store_phi)
+        wait_vmcnt<(HV ? 2 : 1) * NA>();
+      else
+        wait_vmcnt<0>();
+      // direct loads first: the compiler's wait for them then leaves the
+      // next tile's prefetch (issued below) outstanding
       static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
-        const cx<R> v = ldrow<R>(s + boff(I), voff);
-        ps[CV(I)] = ok ? v : zero;
+        const cx<R> p = pf_read(ic<1>{}, I, rowb, voff);
+        ph[CV(I)] = ok ? p : zero;
+        if constexpr (HV) {
+          const cx<R> pd = pf_read(ic<3>{}, I, rowb, voff);
+          dph[CV(I)] = ok ? pd : zero;
+        }
       });
-      if constexpr (HV) {
-        const char *sd = reinterpret_cast<const char *>(A.ckpt_dpsi) + rowb;
-        static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
-          const cx<R> v = ldrow<R>(sd + boff(I), voff);
-          dps[CV(I)] = ok ? v : zero;
-        });
-      }
+      static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+        const cx<R> v = pf_read(ic<0>{}, I, rowb, voff);
+        ps[CV(I)] = ok ? v : zero;
+        if constexpr (HV) {
+          const cx<R> vd = pf_read(ic<2>{}, I, rowb, voff);
+          dps[CV(I)] = ok ? vd : zero;
+        }
+      });
+      wait_lgkm0();  // the buffer is read before the next prefetch overwrites it
+      if (item + nwaves < A.n_items) prefetch(item + nwaves);
     }
 
     if constexpr (STAGE == ST_LAST) {
@@ -651,19 +853,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((
         if constexpr (HV) dph[i] = zero;
       });
       facc += (double)hre;
-    } else if constexpr (STAGE == ST_BWD) {
-      const char *p = reinterpret_cast<const char *>(A.phi) + rowb;
-      static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
-        const cx<R> v = ldrow<R>(p + boff(I), voff);
-        ph[CV(I)] = ok ? v : zero;
-      });
-      if constexpr (HV) {
-        const char *pd = reinterpret_cast<const char *>(A.dphi) + rowb;
-        static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
-          const cx<R> v = ldrow<R>(pd + boff(I), voff);
-          dph[CV(I)] = ok ? v : zero;
-        });
-      }
     }
 
     if constexpr (NEEDB) {
@@ -718,9 +907,19 @@ static int launch_one(const PassArgs &a, int grid, void *stream) {
   constexpr bool NEEDB = STAGE != ST_FWD && (OP == OP_GRAD || OP == OP_HVP);
   constexpr int NT1 = MODE == MODE_DENSE ? 32 : 16;
   constexpr int NE = HV ? 2 * NT1 : NT1;
-  const size_t lds = NEEDB ? size_t(kBlock / 64) * kMaxGates * NE * sizeof(double) : 0;
-  hipLaunchKernelGGL((k_pass<R, NT, MODE, OP, STAGE>), dim3(grid), dim3(kBlock), lds,
-                     (hipStream_t)stream, a);
+  if constexpr (STAGE == ST_BWD) {
+    // one wavefront per block: grid * 4 blocks of 64 threads give the same
+    // wavefronts (and slot indices) as grid blocks of 256 threads
+    constexpr int NPF = __builtin_popcount(Prefetch<R, NT, OP>::mask);
+    const size_t lds = size_t(NPF) * (1 << NT) * 64 * sizeof(cx<R>) +
+                       size_t(kMaxGates) * NE * sizeof(double);
+    hipLaunchKernelGGL((k_pass<R, NT, MODE, OP, STAGE>), dim3(grid * (kBlock / 64)), dim3(64),
+                       lds, (hipStream_t)stream, a);
+  } else {
+    const size_t lds = NEEDB ? size_t(kBlock / 64) * kMaxGates * NE * sizeof(double) : 0;
+    hipLaunchKernelGGL((k_pass<R, NT, MODE, OP, STAGE>), dim3(grid), dim3(kBlock), lds,
+                       (hipStream_t)stream, a);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
