@@ -48,3 +48,4 @@ from .riemann import (  # noqa: F401
     polar,
 )
 from .trust_region import tcg, tr_step  # noqa: F401
+from .evaluate import evaluate  # noqa: F401

@@ -8,24 +8,7 @@ import oracle as O
 
 def oracle_eval(k, pairs, gates, param_of, direction, Ucols, cols, parity=False):
     """Oracle f, egrad, rgrad, ehvp, rhvp (per parameter) summed over cols."""
-    param_of = np.asarray(param_of)
-    inst = gates[param_of]
-    Z = direction[param_of] if direction is not None else np.zeros_like(inst)
-    T, Td = O.tangent_T(k, pairs, inst, Z, Ucols, cols)
-    P = gates.shape[0]
-    Tp = O.per_param(T, param_of, P)
-    Tdp = O.per_param(Td, param_of, P)
-    if parity:
-        Tp = np.where(O.riemann.PARITY_MASK, Tp, 0)
-        Tdp = np.where(O.riemann.PARITY_MASK, Tdp, 0)
-    eg = O.egrad(Tp)
-    rg = O.rgrad(gates, eg, parity)
-    out = dict(f=O.cost(k, pairs, inst, Ucols, cols), egrad=eg, rgrad=rg)
-    if direction is not None:
-        eh = O.egrad(Tdp)
-        out["ehvp"] = eh
-        out["rhvp"] = O.rhvp(gates, eg, eh, direction, parity)
-    return out
+    return O.evaluate(k, pairs, gates, param_of, direction, Ucols, cols, parity=parity)
 
 
 def rel(a, b):

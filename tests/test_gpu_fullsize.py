@@ -1,0 +1,218 @@
+"""GPU parity at the full sizes of the benchmark configurations.
+
+* Configuration 2 (k = 12, 30 independent Haar gates, target exp(-iH/2)):
+  f, gradients and HVP summed over all 4096 basis states, against the oracle
+  values stored by ``tests/golden/make_config2_golden.py``.
+* Configurations 3 (k = 16, two parity sectors of 2^15 states, 7 shared
+  gates / 56 instances) and 4 (k = 16, 72 independent gates) in the launch
+  configuration the benchmark times (whole sectors / all 2^16 basis states,
+  the same chunk sizes): the target is zero except on sampled basis columns
+  (seeded Haar-random unit vectors in the right sector), so every other
+  column contributes exactly zero and the device sums must equal the
+  oracle's sums over the sampled columns.  The samples include the first and
+  last column of each sector and both sides of chunk boundaries.
+* Hessian blocks at k = 16 on short basis ranges: sampled columns of the
+  holomorphic Hessian against the oracle's directional derivatives of T, and
+  the property H x = Hess f[X] over a 64-column range.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as w
+from gpu_helpers import oracle_eval, rel, sector_full_index
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: dict(f=1e-12, v=1e-10), 1: dict(f=1e-5, v=2e-5)}   # RQ_C128, RQ_C64
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_eval.json")
+BENCH_CHUNK = {1: 4096, 0: 2048}        # chunk sizes the benchmark uses (c64, c128)
+PIDX = [0, 3, 12, 15, 5, 6, 9, 10]
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import torch
+    from paper_2506_23775_amd import rq as _rq
+    assert torch.cuda.is_available()
+    _rq.lib()
+    return _rq
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _free():
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def _check(res, ref, dtype, name):
+    tol = TOL[dtype]
+    f, fr = float(res[0]), ref["f"]
+    assert abs(f - fr) <= tol["f"] * max(1.0, abs(fr)), (name, f, fr)
+    for key, r in zip(["egrad", "rgrad", "ehvp", "rhvp"], res[1:]):
+        if key in ref:
+            e = rel(_np(r), ref[key])
+            assert e <= tol["v"], (name, key, e)
+
+
+def sparse_target(rq, k, parity, dtype, picks, rng, window=None):
+    """Device target that is zero except on the picked basis columns.
+
+    picks: (sector, compressed column) in parity mode, (-1, column) otherwise.
+    window: (col_offset, width) to hold only a window of columns.
+    Returns (Target, oracle target columns [2^k, n] complex128, full basis
+    indices of the picks)."""
+    import torch
+    td = rq.torch_dtype(dtype)
+    n = 1 << (k - 1) if parity else 1 << k
+    off, width = window if window is not None else (0, n)
+    ref = torch.zeros((2, n, width) if parity else (n, width), dtype=td, device="cuda")
+    V = w.random_states(rng, n, len(picks))
+    full = np.zeros((1 << k, len(picks)), dtype=np.complex128)
+    cols = []
+    for i, (p, j) in enumerate(picks):
+        v = torch.from_numpy(np.ascontiguousarray(V[:, i])).to(td).cuda()
+        if parity:
+            ref[p, :, j - off] = v
+            full[sector_full_index(k, p, np.arange(n)), i] = V[:, i]
+            cols.append(int(sector_full_index(k, p, [j])[0]))
+        else:
+            ref[:, j - off] = v
+            full[:, i] = V[:, i]
+            cols.append(j)
+    return rq.Target(ref, dtype, parity, col_offset=off), full, np.asarray(cols)
+
+
+# ---------------------------------------------------------------------------
+# configuration 2: all 4096 basis states against stored oracle values
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_config2_full_trace_golden(rq, dtype):
+    with open(GOLDEN) as fh:
+        g = json.load(fh)
+    ref = {"f": g["f"]}
+    for key in ("egrad", "rgrad", "ehvp", "rhvp"):
+        a = np.asarray(g[key])
+        ref[key] = a[..., 0] + 1j * a[..., 1]
+    prob = w.make_problem(2)
+    circ = rq.Circuit(prob.k, prob.pairs, param_of=prob.param_of)
+    tgt = rq.Target.from_dense(prob.U_ref, dtype)
+    _check(rq.rq_hvp(circ, tgt, prob.gates, prob.direction), ref, dtype, "cfg2 hvp")
+    _check(rq.rq_grad(circ, tgt, prob.gates), ref, dtype, "cfg2 grad")
+    f = float(rq.rq_cost(circ, tgt, prob.gates))
+    assert abs(f - ref["f"]) <= TOL[dtype]["f"] * max(1.0, abs(ref["f"]))
+
+
+# ---------------------------------------------------------------------------
+# configurations 3 and 4 at k = 16 in the benchmark's launch configuration
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_config3_sampled_columns_bench_launch(rq, dtype):
+    prob = w.make_problem(3)
+    k = prob.k
+    n = 1 << (k - 1)
+    picks = [(0, 0), (0, 1), (0, 4095), (0, 4096), (0, 20000), (0, n - 1),
+             (1, 0), (1, 8191), (1, 8192), (1, 16385), (1, n - 2), (1, n - 1)]
+    rng = np.random.default_rng([w.configs.SEED, 3, 100])
+    tgt, full, cols = sparse_target(rq, k, True, dtype, picks, rng)
+    circ = rq.Circuit(k, prob.pairs, param_of=prob.param_of, parity=True)
+    ref = oracle_eval(k, prob.pairs, prob.gates, prob.param_of, prob.direction, full, cols,
+                      parity=True)
+    chunk = BENCH_CHUNK[dtype]
+    _check(rq.rq_hvp(circ, tgt, prob.gates, prob.direction, chunk=chunk), ref, dtype, "cfg3 hvp")
+    _check(rq.rq_grad(circ, tgt, prob.gates, chunk=chunk), ref, dtype, "cfg3 grad")
+    f = float(rq.rq_cost(circ, tgt, prob.gates, chunk=chunk))
+    assert abs(f - ref["f"]) <= TOL[dtype]["f"] * max(1.0, abs(ref["f"]))
+    del tgt
+    _free()
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_config4_sampled_columns_full_sweep(rq, dtype):
+    prob = w.make_problem(4)
+    k = prob.k
+    picks = [(-1, j) for j in (0, 63, 64, 4095, 4096, 33333, (1 << k) - 2, (1 << k) - 1)]
+    rng = np.random.default_rng([w.configs.SEED, 4, 100])
+    tgt, full, cols = sparse_target(rq, k, False, dtype, picks, rng)
+    circ = rq.Circuit(k, prob.pairs, param_of=prob.param_of)
+    ref = oracle_eval(k, prob.pairs, prob.gates, prob.param_of, prob.direction, full, cols)
+    _check(rq.rq_hvp(circ, tgt, prob.gates, prob.direction), ref, dtype, "cfg4 hvp")
+    del tgt
+    _free()
+
+
+# ---------------------------------------------------------------------------
+# Hessian blocks at k = 16
+# ---------------------------------------------------------------------------
+
+def _oracle_hessian_column(k, pairs, gates, param_of, Ucols, cols, p, a, b, parity):
+    """Column (p, a, b) of the per-parameter holomorphic Hessian: the
+    directional derivative of T_m (summed per parameter) along E_ab placed on
+    every instance of parameter p."""
+    param_of = np.asarray(param_of)
+    inst = gates[param_of]
+    Z = np.zeros_like(inst)
+    Z[param_of == p, a, b] = 1.0
+    _, Td = O.tangent_T(k, pairs, inst, Z, Ucols, cols)
+    Tp = O.per_param(Td, param_of, gates.shape[0]).reshape(gates.shape[0], 16)
+    return Tp[:, PIDX] if parity else Tp
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("cfg", [4, 3])
+def test_hessian_sampled_columns_k16(rq, dtype, cfg):
+    prob = w.make_problem(cfg)
+    k, parity = prob.k, prob.parity
+    rng = np.random.default_rng([w.configs.SEED, cfg, 101])
+    if parity:
+        j0 = 12340
+        picks = [(1, j0), (1, j0 + 1)]
+        dirs = [(0, 0, 0), (3, 1, 2), (6, 3, 3), (5, 0, 3)]
+    else:
+        j0 = 40000
+        picks = [(-1, j0), (-1, j0 + 1)]
+        dirs = [(0, 0, 0), (35, 1, 2), (71, 3, 3), (50, 2, 0)]
+    tgt, full, cols = sparse_target(rq, k, parity, dtype, picks, rng, window=(j0, 2))
+    circ = rq.Circuit(k, prob.pairs, param_of=prob.param_of, parity=parity)
+    sector = 1 if parity else -1
+    _, _, _, hh, _ = rq.rq_hess_blocks(circ, tgt, prob.gates, range=(sector, j0, 2), chunk=64)
+    hh = _np(hh)
+    d = 8 if parity else 16
+    for (p, a, b) in dirs:
+        e = 4 * a + b
+        ec = PIDX.index(e) if parity else e
+        col = _oracle_hessian_column(k, prob.pairs, prob.gates, prob.param_of, full, cols,
+                                     p, a, b, parity)
+        got = hh[:, :, p, ec].reshape(-1, d)
+        assert rel(got, col) <= TOL[dtype]["v"] * 10, (cfg, p, a, b, rel(got, col))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_hessian_times_direction_equals_hvp_k16(rq, dtype):
+    prob = w.make_problem(4)
+    k = prob.k
+    j0, width = 4000, 64
+    rng = np.random.default_rng([w.configs.SEED, 4, 102])
+    picks = [(-1, j) for j in range(j0, j0 + width)]
+    tgt, _, _ = sparse_target(rq, k, False, dtype, picks, rng, window=(j0, width))
+    circ = rq.Circuit(k, prob.pairs, param_of=prob.param_of)
+    basis_range = (-1, j0, width)
+    _, _, _, _, hr = rq.rq_hess_blocks(circ, tgt, prob.gates, range=basis_range, chunk=64,
+                                       holomorphic=False)
+    hr = _np(hr)
+    x = np.random.default_rng([w.configs.SEED, 4, 103]).standard_normal(hr.shape[0])
+    X = O.tangent_from_real(prob.gates, x)
+    _, _, _, _, rh = rq.rq_hvp(circ, tgt, prob.gates, X, range=basis_range, chunk=64)
+    hx = O.gradient_real(prob.gates, _np(rh))
+    assert rel(hr @ x, hx) <= TOL[dtype]["v"] * 10, rel(hr @ x, hx)
+    assert np.abs(hr - hr.T).max() <= TOL[dtype]["v"] * 100 * np.abs(hr).max()

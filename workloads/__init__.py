@@ -19,6 +19,7 @@ from .hubbard import (  # noqa: F401
 from .circuits import (  # noqa: F401
     brickwall_pairs,
     haar_unitary,
+    random_states,
     haar_gates,
     parity_haar_gates,
     tangent_direction,

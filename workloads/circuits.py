@@ -54,6 +54,13 @@ def haar_unitary(rng: np.random.Generator, m: int) -> np.ndarray:
     return q * (d / np.abs(d))[None, :]
 
 
+def random_states(rng: np.random.Generator, dim: int, n: int) -> np.ndarray:
+    """n Haar-random unit vectors of dimension dim, as the columns of a
+    [dim, n] complex128 array (normalised complex Gaussians)."""
+    z = _complex_gaussian(rng, (dim, n))
+    return z / np.linalg.norm(z, axis=0, keepdims=True)
+
+
 def haar_gates(rng: np.random.Generator, n: int) -> np.ndarray:
     return np.stack([haar_unitary(rng, 4) for _ in range(n)])
 
