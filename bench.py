@@ -137,6 +137,43 @@ def cpu_baseline(prob, ncols=2, budget_s=15.0):
                        f"({dt * reps:.1f} s), extrapolated x{(1 << k) // ncols}")
 
 
+def serving_run(rq, n_requests, rate_hz, seed_requests=None):
+    """Configuration 5: a Poisson stream of f / f+grad / f+grad+HVP requests
+    of mixed size (k = 8..16, depth 3..9), served by the continuous-batching
+    loop in complex64 with FP64 accumulation.  Latency = completion - arrival
+    (end to end, includes the request's target preparation on the device) and
+    completion - admission (evaluation only)."""
+    import torch
+
+    import workloads as w
+    from paper_2506_23775_amd import serving
+    warm = serving.make_gpu_request(dict(rid=10**6, arrival=0.0, k=8, depth=3, U=4.0, t=0.5,
+                                         op="hvp"), rq.RQ_C64)
+    serving.ContinuousBatcher(serving.GpuExecutor(rq.RQ_C64), hbm_budget=1 << 30).run([warm])
+    descs = w.configs.serving_requests(n_requests, rate_hz)
+    reqs = [serving.make_gpu_request(d, rq.RQ_C64) for d in descs]
+    ex = serving.GpuExecutor(rq.RQ_C64, chunk=4096)
+    batcher = serving.ContinuousBatcher(ex, hbm_budget=96 << 30, max_active=8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = batcher.run(reqs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = serving.latency_stats(done)
+    lat = {op: {k: (round(v, 2) if isinstance(v, float) else v) for k, v in st.items()}
+           for op, st in stats.items()}
+    ks = {}
+    for d in descs:
+        ks[str(d["k"])] = ks.get(str(d["k"]), 0) + 1
+    return dict(workload="cfg5: Poisson arrivals of f / f+grad / f+grad+HVP requests, "
+                         "k in {8..16}, brick-wall depth in {3,5,7,9}, Hubbard targets "
+                         "(dense exp(-iHt) for k <= 12, 20-step Strang Trotter on the device "
+                         "beyond), c64 states + FP64 accumulation",
+                requests=len(done), rate_hz=rate_hz, seconds=round(dt, 3),
+                throughput_req_per_s=round(len(done) / dt, 3), k_mix=ks,
+                peak_hbm_GiB=round(batcher.peak_used / 2**30, 2), latency_ms=lat)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +184,9 @@ def main():
     ap.add_argument("--trotter-steps", type=int, default=200)
     ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=16,
+                    help="requests in the configuration-5 serving leg (0: skip it)")
+    ap.add_argument("--serving-rate", type=float, default=1.0, help="Poisson arrival rate, 1/s")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 2 GiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -229,6 +269,13 @@ def main():
         out["c64_rel_error_vs_c128"] = {k: float(f"{v:.3e}") for k, v in err.items()}
         dom128 = max(r128["prof"].items(), key=lambda kv: kv[1]["ms"])[0]
         out["roofline_c128"] = roofline(r128["prof"], dom128)
+
+    if args.serving_requests > 0:
+        del tgt64, tgt128
+        torch.cuda.empty_cache()
+        log(f"[bench] serving leg: {args.serving_requests} requests at {args.serving_rate}/s")
+        out["serving"] = serving_run(rq, args.serving_requests, args.serving_rate)
+        log(f"[bench] serving: {out['serving']['throughput_req_per_s']} req/s")
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
