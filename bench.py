@@ -36,12 +36,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gpu_run(rq, torch, circ, target, prob, steps, warmup, chunk):
+def gpu_run(rq, torch, circ, target, prob, steps, warmup, chunk, basis_range=None):
     ws_need = rq.lib().rq_workspace_bytes(rq.C.byref(circ._c), rq.RQ_OP_HVP, target.dtype, chunk)
     ws = rq.Workspace(ws_need)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        rq.rq_hvp(circ, target, prob.gates, prob.direction, chunk=chunk, workspace=ws)
+        rq.rq_hvp(circ, target, prob.gates, prob.direction, range=basis_range, chunk=chunk,
+                  workspace=ws)
     torch.cuda.synchronize()
     rq.rq_profile_read()                     # drop anything recorded so far
     rq.rq_profile_enable(True)
@@ -52,7 +53,8 @@ def gpu_run(rq, torch, circ, target, prob, steps, warmup, chunk):
     out = None
     for i in range(steps):
         evs[i][0].record(stream)
-        out = rq.rq_hvp(circ, target, prob.gates, prob.direction, chunk=chunk, workspace=ws)
+        out = rq.rq_hvp(circ, target, prob.gates, prob.direction, range=basis_range, chunk=chunk,
+                        workspace=ws)
         evs[i][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -184,6 +186,8 @@ def main():
     ap.add_argument("--trotter-steps", type=int, default=200)
     ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sampled-vectors", type=int, default=256,
+                    help="random vectors per parity sector in the sampled-trace leg (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=16,
                     help="requests in the configuration-5 serving leg (0: skip it)")
     ap.add_argument("--serving-rate", type=float, default=1.0, help="Poisson arrival rate, 1/s")
@@ -250,6 +254,27 @@ def main():
     out["roofline"] = roofline(r64["prof"], dom)
     if args.chunk == 4096:
         out["roofline"]["traffic"] = measured_traffic(f"{dom[0]}/{dom[1]}")
+
+    if args.sampled_vectors > 0:
+        # trace over random vectors instead of the 2^16 basis states (same
+        # kernels, input states given): time and error against the exact sum
+        R = args.sampled_vectors
+        log(f"[bench] sampled trace: {R} vectors per sector")
+        tgt_s = rq.sampled_target(prob.k, R, np.random.default_rng([w.configs.SEED, 3, 200]),
+                                  dtype=rq.RQ_C64, parity=True, gate_list=prob.trotter)
+        rs = gpu_run(rq, torch, circ, tgt_s, prob, args.steps, args.warmup,
+                     min(args.chunk, max(64, (R + 63) // 64 * 64)), basis_range=(-1, 0, R))
+        names = ["f", "egrad", "rgrad", "ehvp", "rhvp"]
+        err = {}
+        for n, a, b in zip(names, rs["result"], r64["result"]):
+            nb = np.linalg.norm(b)
+            err[n] = float(f"{np.linalg.norm(a / R - b) / (nb if nb else 1.0):.3e}")
+        out["sampled_trace"] = {
+            "vectors_per_sector": R, "kind": "complex Rademacher", "dtype": "c64",
+            "evals_per_s": round(args.steps / rs["seconds"], 3),
+            "ms_per_step": round(rs["seconds"] / args.steps * 1e3, 3),
+            "rel_error_vs_exact_trace": err}
+        del tgt_s
 
     if tgt128 is not None:
         log("[bench] c128 timed run")

@@ -99,19 +99,33 @@ typedef struct rq_circuit {
  *               blocks (U conserves parity), x', j' < 2^(k-1).
  * Only the columns of the requested basis range are read, so ref may point
  * (by offset) into a narrower window of columns.
- * dtype is also the state precision of the evaluation. */
+ * dtype is also the state precision of the evaluation.
+ *
+ * Input states (sampling the trace over random vectors instead of the basis,
+ * the follow-up outlined in Sec. "Conclusions"): if inputs is not NULL,
+ * summand j starts from the state |psi_j> = inputs column j instead of |j>,
+ * laid out like ref (inputs[x*in_ld + j], or
+ * inputs[s*in_sector_stride + x'*in_ld + j'] for a sector-s state in parity
+ * mode), and ref column j must then hold U|psi_j>.  Every output becomes the
+ * same function of the sum over j of <psi_j| U^dagger C(G) |psi_j>; scaling
+ * it into a trace estimate is left to the caller.  NULL inputs: in_ld and
+ * in_sector_stride are ignored. */
 typedef struct rq_target {
   int32_t dtype;
   int32_t reserved;
   const void *ref;
   int64_t ld;
   int64_t sector_stride;
+  const void *inputs;
+  int64_t in_ld;
+  int64_t in_sector_stride;
 } rq_target;
 
 /* Range of basis states of the trace sum.  General mode: j in
  * [begin, begin+count) of [0, 2^k), sector must be -1.  Parity mode: sector
  * 0 or 1 and j' in [begin, begin+count) of [0, 2^(k-1)), or sector -1 with
- * begin 0 and count 2^(k-1) for both sectors.  A NULL range is the full
+ * begin 0 and count 2^(k-1) for both sectors (with input states: sector -1
+ * takes [begin, begin+count) in both sectors).  A NULL range is the full
  * trace.  count 0 is allowed (all outputs are then the empty sum, projected). */
 typedef struct rq_range {
   int32_t sector;

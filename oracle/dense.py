@@ -96,33 +96,43 @@ def unit_columns(k: int, cols) -> np.ndarray:
     return E
 
 
+def _initial(k, cols, inputs):
+    """Starting states of the summands: |j> for j in cols (Sec. "Objective
+    function and matrix-free evaluation"), or the given input states psi_j
+    (2^k x n) when the sum runs over other vectors (sampling over random
+    vectors, Sec. "Conclusions"); Ucols must then hold U psi_j."""
+    if inputs is not None:
+        return np.asarray(inputs, dtype=np.complex128)
+    return unit_columns(k, _cols(k, cols))
+
+
 # ---------------------------------------------------------------------------
 # Cost
 # ---------------------------------------------------------------------------
 
-def h_trace(k, pairs, gates, Ucols, cols=None) -> complex:
+def h_trace(k, pairs, gates, Ucols, cols=None, inputs=None) -> complex:
     """h_S = sum_{j in S} <j| U^dagger C(G) |j>  (complex; holomorphic in the
-    gate entries).  ``Ucols`` = U|j> for j in S (2^k x |S|)."""
-    cols = _cols(k, cols)
-    Psi = unit_columns(k, cols)
+    gate entries).  ``Ucols`` = U|j> for j in S (2^k x |S|).  With
+    ``inputs``: sum over the input states psi_j instead of |j>."""
+    Psi = _initial(k, cols, inputs)
     for pair, G in zip(pairs, gates):
         Psi = apply_gate(Psi, k, pair, G)
     return complex(np.sum(np.conj(Ucols) * Psi))
 
 
-def cost(k, pairs, gates, Ucols, cols=None) -> float:
+def cost(k, pairs, gates, Ucols, cols=None, inputs=None) -> float:
     """f = -Re Tr[U^dagger C(G)] (eq. for the target function), restricted to
-    the basis states in ``cols``."""
-    return -h_trace(k, pairs, gates, Ucols, cols).real
+    the basis states in ``cols`` (or summed over input states)."""
+    return -h_trace(k, pairs, gates, Ucols, cols, inputs).real
 
 
 # ---------------------------------------------------------------------------
 # Prefix / suffix products and hole contractions
 # ---------------------------------------------------------------------------
 
-def forward_states(k, pairs, gates, cols=None):
+def forward_states(k, pairs, gates, cols=None, inputs=None):
     """Psi_l = E_l ... E_1 |j>, l = 0..N, for j in cols (prefix products)."""
-    Psi = [unit_columns(k, _cols(k, cols))]
+    Psi = [_initial(k, cols, inputs)]
     for pair, G in zip(pairs, gates):
         Psi.append(apply_gate(Psi[-1], k, pair, G))
     return Psi
@@ -155,28 +165,27 @@ def hole_contraction(k, pair, Lam: np.ndarray, Psi: np.ndarray) -> np.ndarray:
     return legs(Lam) @ legs(Psi).T
 
 
-def euclidean_T(k, pairs, gates, Ucols, cols=None) -> np.ndarray:
+def euclidean_T(k, pairs, gates, Ucols, cols=None, inputs=None) -> np.ndarray:
     """T_l = d h_S / d G_l for every gate instance l (N x 4 x 4 complex).
 
     With B_l = E_{l-1}...E_1 and A_l = E_N...E_{l+1},
     h = Tr[E_l (B_l U^dagger A_l)] restricted to S, so T_l is the partial trace
     of B_l U^dagger A_l with the two legs of gate l left open (Sec. "Gradient
     and Hessian tensor diagrams")."""
-    Psi = forward_states(k, pairs, gates, cols)
+    Psi = forward_states(k, pairs, gates, cols, inputs)
     Lam = backward_states(k, pairs, gates, Ucols)
     N = len(pairs)
     return np.stack([hole_contraction(k, pairs[l], Lam[l + 1], Psi[l]) for l in range(N)])
 
 
-def tangent_T(k, pairs, gates, Z, Ucols, cols=None):
+def tangent_T(k, pairs, gates, Z, Ucols, cols=None, inputs=None):
     """(T, Tdot): T as in euclidean_T and its directional derivative Tdot along
     G_l -> G_l + eps Z_l (all instances), evaluated with dual numbers: every
     prefix/suffix product is carried as a pair (value, derivative).  This is
     the derivative of the directed gradient that the appendix on
     Hessian-vector products differentiates once more."""
-    cols_ = _cols(k, cols)
     N = len(pairs)
-    Psi = [unit_columns(k, cols_)]
+    Psi = [_initial(k, cols, inputs)]
     dPsi = [np.zeros_like(Psi[0])]
     for l in range(N):
         Psi.append(apply_gate(Psi[l], k, pairs[l], gates[l]))
@@ -197,7 +206,7 @@ def tangent_T(k, pairs, gates, Z, Ucols, cols=None):
     return T, Td
 
 
-def hessian_holomorphic(k, pairs, gates, Ucols, cols=None, mask=None) -> np.ndarray:
+def hessian_holomorphic(k, pairs, gates, Ucols, cols=None, mask=None, inputs=None) -> np.ndarray:
     """All second derivatives d^2 h / dG_l[a,b] dG_m[c,d] (N x 4 x 4 x N x 4 x 4).
 
     Column (l, a, b) of this matrix is the derivative of every T_m along the
@@ -215,6 +224,6 @@ def hessian_holomorphic(k, pairs, gates, Ucols, cols=None, mask=None) -> np.ndar
                     continue
                 Zs[:] = 0
                 Zs[l, a, b] = 1.0
-                _, Td = tangent_T(k, pairs, gates, Zs, Ucols, cols)
+                _, Td = tangent_T(k, pairs, gates, Zs, Ucols, cols, inputs)
                 H[:, :, :, l, a, b] = Td
     return H

@@ -21,14 +21,17 @@ from .dense import cost, tangent_T
 from .riemann import PARITY_MASK, egrad, per_param, rgrad, rhvp
 
 
-def evaluate(k, pairs, gates, param_of, direction, Ucols, cols=None, parity=False) -> dict:
+def evaluate(k, pairs, gates, param_of, direction, Ucols, cols=None, parity=False,
+             inputs=None) -> dict:
     """Returns dict(f, egrad, rgrad[, ehvp, rhvp]) for gates [P,4,4] with
     instances param_of[l], target columns Ucols = U|j> for j in cols (all
-    2^k basis states when cols is None), and an optional direction [P,4,4]."""
+    2^k basis states when cols is None), and an optional direction [P,4,4].
+    With ``inputs`` (2^k x n) the sum runs over those states psi_j instead,
+    and Ucols holds U psi_j."""
     param_of = np.asarray(param_of)
     inst = gates[param_of]
     Z = direction[param_of] if direction is not None else np.zeros_like(inst)
-    T, Td = tangent_T(k, pairs, inst, Z, Ucols, cols)
+    T, Td = tangent_T(k, pairs, inst, Z, Ucols, cols, inputs)
     P = gates.shape[0]
     Tp = per_param(T, param_of, P)
     Tdp = per_param(Td, param_of, P)
@@ -36,7 +39,8 @@ def evaluate(k, pairs, gates, param_of, direction, Ucols, cols=None, parity=Fals
         Tp = np.where(PARITY_MASK, Tp, 0)
         Tdp = np.where(PARITY_MASK, Tdp, 0)
     eg = egrad(Tp)
-    out = dict(f=cost(k, pairs, inst, Ucols, cols), egrad=eg, rgrad=rgrad(gates, eg, parity))
+    out = dict(f=cost(k, pairs, inst, Ucols, cols, inputs), egrad=eg,
+               rgrad=rgrad(gates, eg, parity))
     if direction is not None:
         eh = egrad(Tdp)
         out["ehvp"] = eh

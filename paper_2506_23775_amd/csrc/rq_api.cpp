@@ -32,8 +32,8 @@ struct HessArgs {
 int launch_hess_pass(int is_double, int nt, int mode, const HessArgs &a, int grid, void *s);
 int launch_hole(int is_double, const void *src, void *dst, int64_t rows, int64_t ld, int ncols,
                 int nd, int k, int qh, int ql, int parity, int sector, void *s);
-int launch_target_conj(int is_double, const void *ref, int64_t ld_ref, int64_t col0, void *dst,
-                       int64_t rows, int64_t ld, int ncols, void *s);
+int launch_copy_cols(int is_double, const void *src, int64_t ld_src, int64_t col0, void *dst,
+                     int64_t rows, int64_t ld, int ncols, bool conj, void *s);
 int launch_onehot(int is_double, void *dst, int64_t rows, int64_t ld, int64_t col0, int ncols,
                   void *s);
 int launch_accum_rows(const double *slots, int rows, int nslots, double *acc, void *s);
@@ -435,7 +435,10 @@ struct Range {
   int64_t begin, count;
 };
 
-int check_range(const rq_circuit *c, const Layout &L, const rq_range *r, Range &R) {
+// inputs: input states replace the basis states; then sector -1 in parity
+// mode takes the same column range in both sectors.
+int check_range(const rq_circuit *c, const Layout &L, const rq_range *r, Range &R,
+                bool inputs = false) {
   const int64_t ncol = int64_t(1) << L.kq;
   if (!r) {
     R.begin = 0;
@@ -459,7 +462,7 @@ int check_range(const rq_circuit *c, const Layout &L, const rq_range *r, Range &
     R.nsec = 1;
     R.sectors[0] = 0;
   } else if (r->sector == -1) {
-    if (r->begin != 0 || r->count != ncol)
+    if (!inputs && (r->begin != 0 || r->count != ncol))
       return fail(RQ_EINVAL, "sector -1 requires the full range of both sectors");
     R.nsec = 2;
     R.sectors[0] = 0;
@@ -490,10 +493,11 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
   if (reinterpret_cast<uintptr_t>(ex->workspace) & 255)
     return fail(RQ_EINVAL, "workspace must be 256-byte aligned");
   Range R;
-  st = check_range(c, L, range, R);
+  st = check_range(c, L, range, R, t->inputs != nullptr);
   if (st) return st;
   const int64_t ncol = int64_t(1) << L.kq;
   if (t->ld < 1) return fail(RQ_EINVAL, "target ld must be positive");
+  if (t->inputs && t->in_ld < 1) return fail(RQ_EINVAL, "input-state ld must be positive");
   (void)ncol;
   st = prepare_upload(c, L, gates, dir);
   if (st) return st;
@@ -540,14 +544,19 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
       a.ncols = ncols;
       a.ncg = ncg;
       a.n_items = items;
+      // input states of the chunk (NULL: one-hot basis states)
+      const void *in0 = t->inputs ? static_cast<const char *>(t->inputs) +
+                                        (size_t(sector) * size_t(t->in_sector_stride) + size_t(j0)) * L.esize
+                                  : nullptr;
       // forward passes
       for (int p = 0; p + 1 < np; ++p) {
         fill_pass(a, L.plan[p], L);
+        a.ld_src = p == 0 ? t->in_ld : L.chunk;
         if (L.op == OP_COST) {
-          a.src_psi = p == 0 ? nullptr : buf(0);
+          a.src_psi = p == 0 ? in0 : buf(0);
           a.dst_psi = buf(0);
         } else {
-          a.src_psi = p == 0 ? nullptr : buf(nst * (p - 1));
+          a.src_psi = p == 0 ? in0 : buf(nst * (p - 1));
           a.src_dpsi = p == 0 ? nullptr : (nst == 2 ? buf(nst * (p - 1) + 1) : nullptr);
           a.dst_psi = buf(nst * p);
           a.dst_dpsi = nst == 2 ? buf(nst * p + 1) : nullptr;
@@ -558,10 +567,11 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
       }
       // last pass: forward, overlap with U|j>, first backward pass
       fill_pass(a, L.plan[np - 1], L);
+      a.ld_src = np == 1 ? t->in_ld : L.chunk;
       if (L.op == OP_COST) {
-        a.src_psi = np == 1 ? nullptr : buf(0);
+        a.src_psi = np == 1 ? in0 : buf(0);
       } else {
-        a.src_psi = np == 1 ? nullptr : buf(nst * (np - 2));
+        a.src_psi = np == 1 ? in0 : buf(nst * (np - 2));
         a.src_dpsi = (np == 1 || nst == 1) ? nullptr : buf(nst * (np - 2) + 1);
         a.phi = buf(nst * (np - 1));
         a.dphi = nst == 2 ? buf(nst * (np - 1) + 1) : nullptr;
@@ -674,7 +684,7 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
   if (reinterpret_cast<uintptr_t>(ex->workspace) & 255)
     return fail(RQ_EINVAL, "workspace must be 256-byte aligned");
   Range R;
-  st = check_range(c, L, range, R);
+  st = check_range(c, L, range, R, t->inputs != nullptr);
   if (st) return st;
   char *ws = static_cast<char *>(ex->workspace);
   hipStream_t s = static_cast<hipStream_t>(ex->stream);
@@ -764,6 +774,7 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
   std::memset(&a, 0, sizeof(a));
   a.kq = L.kq;
   a.ld = H.chunk;
+  a.ld_src = H.chunk;
   HessArgs ha;
   std::memset(&ha, 0, sizeof(ha));
   ha.coef = ws + H.off_coef;
@@ -790,9 +801,17 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
       a.ncg = ncg;
       a.n_items = (int)((int64_t(1) << (L.kq - 2)) * ncg);
       const int grid2 = (int)((std::min<int64_t>(a.n_items, kMaxWaves) + 3) / 4);
-      // psi before every gate along pi (slab t = before the t-th gate of pi)
-      if (launch_onehot(L.is_double, slab(psi, 0), H.rows, H.chunk, j0, ncols, s))
+      // psi before every gate along pi (slab t = before the t-th gate of pi),
+      // starting from |j> or from the input states
+      if (t->inputs) {
+        const char *in = static_cast<const char *>(t->inputs) +
+                         size_t(sector) * size_t(t->in_sector_stride) * L.esize;
+        if (launch_copy_cols(L.is_double, in, t->in_ld, j0, slab(psi, 0), H.rows, H.chunk, ncols,
+                             false, s))
+          return fail(RQ_EHIP, "input copy launch failed");
+      } else if (launch_onehot(L.is_double, slab(psi, 0), H.rows, H.chunk, j0, ncols, s)) {
         return fail(RQ_EHIP, "onehot launch failed");
+      }
       a.coef = ws + H.off_coef;
       for (int t = 1; t < N; ++t) {
         fill_pass(a, single[order[t - 1]], L);
@@ -802,8 +821,8 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
           return fail(RQ_EHIP, "forward state launch failed");
       }
       // phi at the output side of every gate along pi (slab = instance)
-      if (launch_target_conj(L.is_double, ref, t->ld, j0, slab(phi, order[N - 1]), H.rows, H.chunk,
-                             ncols, s))
+      if (launch_copy_cols(L.is_double, ref, t->ld, j0, slab(phi, order[N - 1]), H.rows, H.chunk,
+                           ncols, true, s))
         return fail(RQ_EHIP, "target launch failed");
       a.coef = ws + H.off_coefT;
       for (int t = N - 1; t >= 1; --t) {
@@ -935,6 +954,7 @@ int rq_apply_circuit(const rq_circuit *circuit, const double *gates, void *d_sta
   std::memset(&a, 0, sizeof(a));
   a.coef = ws + L.off_coef;
   a.ld = ld;
+  a.ld_src = ld;
   a.sector = L.parity ? sector : 0;
   a.ncols = (int)n_states;
   int items, ncg;

@@ -183,18 +183,21 @@ __global__ void k_hole(const cx<R> *__restrict__ src, cx<R> *__restrict__ dst, i
   }
 }
 
-// phi at the output side of the last gate: conj(U|j>), zero in padding columns.
+// Columns col0..col0+ncols of a slab (row stride ld_src) into a chunk slab,
+// conjugated for phi = conj(U|j>) at the output side of the last gate; zero in
+// padding columns.
 template <typename R>
-__global__ void k_target_conj(const cx<R> *__restrict__ ref, int64_t ld_ref, int64_t col0,
-                              cx<R> *__restrict__ dst, int64_t rows, int64_t ld, int ncols) {
+__global__ void k_copy_cols(const cx<R> *__restrict__ src, int64_t ld_src, int64_t col0,
+                            cx<R> *__restrict__ dst, int64_t rows, int64_t ld, int ncols,
+                            int conj) {
   const int64_t total = rows * ld;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int64_t c = i % ld, x = i / ld;
     cx<R> v{R(0), R(0)};
     if (c < ncols) {
-      v = ref[x * ld_ref + col0 + c];
-      v.y = -v.y;
+      v = src[x * ld_src + col0 + c];
+      if (conj) v.y = -v.y;
     }
     dst[i] = v;
   }
@@ -401,15 +404,17 @@ int launch_hole(int is_double, const void *src, void *dst, int64_t rows, int64_t
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_target_conj(int is_double, const void *ref, int64_t ld_ref, int64_t col0, void *dst,
-                       int64_t rows, int64_t ld, int ncols, void *s) {
+int launch_copy_cols(int is_double, const void *src, int64_t ld_src, int64_t col0, void *dst,
+                     int64_t rows, int64_t ld, int ncols, bool conj, void *s) {
   const int g = grid_of(rows * ld);
   if (is_double)
-    hipLaunchKernelGGL(k_target_conj<double>, dim3(g), dim3(256), 0, (hipStream_t)s,
-                       (const cx<double> *)ref, ld_ref, col0, (cx<double> *)dst, rows, ld, ncols);
+    hipLaunchKernelGGL(k_copy_cols<double>, dim3(g), dim3(256), 0, (hipStream_t)s,
+                       (const cx<double> *)src, ld_src, col0, (cx<double> *)dst, rows, ld, ncols,
+                       conj ? 1 : 0);
   else
-    hipLaunchKernelGGL(k_target_conj<float>, dim3(g), dim3(256), 0, (hipStream_t)s,
-                       (const cx<float> *)ref, ld_ref, col0, (cx<float> *)dst, rows, ld, ncols);
+    hipLaunchKernelGGL(k_copy_cols<float>, dim3(g), dim3(256), 0, (hipStream_t)s,
+                       (const cx<float> *)src, ld_src, col0, (cx<float> *)dst, rows, ld, ncols,
+                       conj ? 1 : 0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -34,7 +34,8 @@ struct GateRef {
 
 struct PassArgs {
   const void *coef;        // per-instance coefficients (state precision)
-  const void *src_psi;     // FWD / LAST input states (NULL: one-hot |j>)
+  const void *src_psi;     // FWD / LAST input states (NULL: one-hot |j>),
+                           // row stride ld_src
   const void *src_dpsi;    // HVP tangent input (NULL: zero)
   void *dst_psi;           // FWD output (checkpoint / in-place apply)
   void *dst_dpsi;
@@ -46,6 +47,7 @@ struct PassArgs {
   double *slots;           // FP64 partials [inst][entry][slot]
   double *fslots;          // FP64 partials of f [slot]
   int64_t ld;              // row stride of the chunk slabs (elements)
+  int64_t ld_src;          // row stride of src_psi (elements)
   int64_t ld_ref;          // row stride of ref (elements)
   int64_t col0;            // basis column of chunk column 0
   int32_t ncols;           // valid columns of the chunk

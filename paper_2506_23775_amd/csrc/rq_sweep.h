@@ -662,6 +662,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((
     });
     return o;
   };
+  // byte offset of local amplitude I in the input slab (row stride ld_src)
+  auto soff = [&](auto I) __attribute__((always_inline)) {
+    int64_t o = 0;
+    static_for<0, NT>([&](auto B) __attribute__((always_inline)) {
+      if constexpr ((CV(I) >> CV(B)) & 1) o += (int64_t(1) << A.pos[CV(B)]) * A.ld_src * ES;
+    });
+    return o;
+  };
   auto roff = [&](auto I) __attribute__((always_inline)) {
     int64_t o = 0;
     static_for<0, NT>([&](auto B) __attribute__((always_inline)) {
@@ -764,9 +772,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((
     cx<R> ps[NA], dps[NA], ph[NA], dph[NA];
     if constexpr (NEEDF) {
       if (A.src_psi) {
-        const char *s = reinterpret_cast<const char *>(A.src_psi) + rowb;
+        const char *s = reinterpret_cast<const char *>(A.src_psi) + base * A.ld_src * ES;
         static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
-          const cx<R> v = ldrow<R>(s + boff(I), voff);
+          const cx<R> v = ldrow<R>(s + soff(I), voff);
           ps[CV(I)] = ok ? v : zero;
         });
       } else {

@@ -38,7 +38,8 @@ class _Circuit(C.Structure):
 
 class _Target(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("reserved", C.c_int32), ("ref", C.c_void_p),
-                ("ld", C.c_int64), ("sector_stride", C.c_int64)]
+                ("ld", C.c_int64), ("sector_stride", C.c_int64), ("inputs", C.c_void_p),
+                ("in_ld", C.c_int64), ("in_sector_stride", C.c_int64)]
 
 
 class _Range(C.Structure):
@@ -183,25 +184,42 @@ def sector_rows(k: int, p: int) -> np.ndarray:
 
 @dataclass
 class Target:
-    """Device target columns.  ``ref``: general [2^k, 2^k] (U[x][j]) or parity
-    [2, 2^(k-1), 2^(k-1)] sector blocks, complex64 / complex128 on cuda."""
+    """Device target columns.  ``ref``: general [2^k, width] (U[x][j]) or
+    parity [2, 2^(k-1), width] sector blocks, complex64 / complex128 on cuda.
+    ``inputs`` (optional, same shape as ref): input states psi_j replacing the
+    basis states |j>; ref column j then holds U psi_j."""
 
     ref: torch.Tensor
     dtype: int
     parity: bool
     col_offset: int = 0     # ref holds the columns [col_offset, col_offset + width)
+    inputs: Optional[torch.Tensor] = None
+
+    @staticmethod
+    def _geometry(t: torch.Tensor, parity: bool):
+        if t.dtype not in (torch.complex64, torch.complex128) or not t.is_contiguous():
+            raise ValueError("target / input slabs must be contiguous complex tensors")
+        if parity:
+            if t.dim() != 3 or t.shape[0] != 2:
+                raise ValueError("parity slabs are [2, 2^(k-1), width]")
+            return t.shape[2], t.shape[1] * t.shape[2]
+        if t.dim() != 2:
+            raise ValueError("general slabs are [2^k, width]")
+        return t.shape[1], 0
 
     def struct(self):
-        if self.parity:
-            ld = self.ref.shape[2]
-            ss = self.ref.shape[1] * self.ref.shape[2]
-        else:
-            ld = self.ref.shape[1]
-            ss = 0
+        ld, ss = self._geometry(self.ref, self.parity)
         esize = self.ref.element_size()
         # the C ABI addresses column j at ref + x*ld + j: shift the base so that
         # a window of columns starting at col_offset is addressed by global j
-        return _Target(self.dtype, 0, self.ref.data_ptr() - self.col_offset * esize, ld, ss)
+        ref = self.ref.data_ptr() - self.col_offset * esize
+        if self.inputs is None:
+            return _Target(self.dtype, 0, ref, ld, ss, None, 0, 0)
+        if self.inputs.shape != self.ref.shape or self.inputs.dtype != self.ref.dtype:
+            raise ValueError("inputs must have the shape and dtype of ref")
+        ild, iss = self._geometry(self.inputs, self.parity)
+        return _Target(self.dtype, 0, ref, ld, ss,
+                       self.inputs.data_ptr() - self.col_offset * esize, ild, iss)
 
     @staticmethod
     def from_dense(U: np.ndarray, dtype: int = RQ_C128, parity: bool = False, device="cuda"):
@@ -449,6 +467,51 @@ def build_trotter_target(k: int, gate_list, dtype: int = RQ_C128, parity: bool =
         ref = torch.eye(n, dtype=td, device=device)
         rq_apply_circuit(circ, gates, ref, dtype=dtype, sector=-1)
     return Target(ref, dtype, parity)
+
+
+def sampled_target(k: int, n_samples: int, rng: np.random.Generator, *, dtype: int = RQ_C128,
+                   parity: bool = False, gate_list=None, U: Optional[np.ndarray] = None,
+                   kind: str = "rademacher", device="cuda") -> Target:
+    """Input states and target columns for estimating the trace over random
+    vectors instead of the 2^k basis states (the follow-up outlined in Sec.
+    "Conclusions").  Column r holds z_r with independent entries, either
+    complex Rademacher (uniform on {1, i, -1, -i}) or standard complex
+    Gaussian, so that E[z z^dagger] = I and E[z^dagger A z] = Tr A; in parity
+    mode each sector block gets its own n_samples vectors of the sector
+    dimension.  The random numbers are drawn on the host from ``rng`` and
+    passed in; the target columns U z_r are built on the device by applying
+    ``gate_list`` with rq_apply_circuit, or (small k) from a dense host ``U``.
+    Scale the library's sums by 1 / n_samples for the estimate."""
+    dim = 1 << (k - 1) if parity else 1 << k
+    shape = (2, dim, n_samples) if parity else (dim, n_samples)
+    if kind == "rademacher":
+        Z = (1j ** rng.integers(0, 4, size=shape)).astype(np.complex128)
+    elif kind == "gaussian":
+        Z = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
+    else:
+        raise ValueError("kind must be 'rademacher' or 'gaussian'")
+    td = torch_dtype(dtype)
+    inputs = torch.from_numpy(np.ascontiguousarray(Z)).to(td).to(device)
+    if gate_list is not None:
+        pairs = [p for p, _ in gate_list]
+        gates = np.stack([G for _, G in gate_list])
+        circ = Circuit(k, pairs, parity=parity)
+        ref = inputs.clone()
+        if parity:
+            for p in (0, 1):
+                rq_apply_circuit(circ, gates, ref[p], dtype=dtype, sector=p)
+        else:
+            rq_apply_circuit(circ, gates, ref, dtype=dtype, sector=-1)
+    elif U is not None:
+        U = np.asarray(U)
+        if parity:
+            Y = np.stack([U[np.ix_(sector_rows(k, p), sector_rows(k, p))] @ Z[p] for p in (0, 1)])
+        else:
+            Y = U @ Z
+        ref = torch.from_numpy(np.ascontiguousarray(Y)).to(td).to(device)
+    else:
+        raise ValueError("give the target as gate_list or U")
+    return Target(ref, dtype, parity, inputs=inputs)
 
 
 STAGES = ("fwd", "last", "bwd")
