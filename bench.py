@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sampled-vectors", type=int, default=256,
                     help="random vectors per parity sector in the sampled-trace leg (0: skip)")
+    ap.add_argument("--tr-iters", type=int, default=5,
+                    help="trust-region iterations in the configuration-2 leg (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=16,
                     help="requests in the configuration-5 serving leg (0: skip it)")
     ap.add_argument("--serving-rate", type=float, default=1.0, help="Poisson arrival rate, 1/s")
@@ -269,8 +271,8 @@ def main():
         for n, a, b in zip(names[1:], rs["result"][1:], r64["result"][1:]):
             nb = np.linalg.norm(b)
             err[n] = float(f"{np.linalg.norm(a / R - b) / (nb if nb else 1.0):.3e}")
-        f_est = float(rs["result"][0][0]) / R
-        f_ex = float(r64["result"][0][0])
+        f_est = float(rs["result"][0]) / R
+        f_ex = float(r64["result"][0])
         out["sampled_trace"] = {
             "vectors_per_sector": R, "kind": "complex Rademacher", "dtype": "c64",
             "evals_per_s": round(args.steps / rs["seconds"], 3),
@@ -300,6 +302,30 @@ def main():
         out["c64_rel_error_vs_c128"] = {k: float(f"{v:.3e}") for k, v in err.items()}
         dom128 = max(r128["prof"].items(), key=lambda kv: kv[1]["ms"])[0]
         out["roofline_c128"] = roofline(r128["prof"], dom128)
+
+    if args.tr_iters > 0:
+        # configuration 2 (k = 12, 30 gates): full Riemannian trust-region
+        # iterations, each with the 480 x 480 Hessian from rq_hess_blocks
+        log(f"[bench] trust-region leg: {args.tr_iters} iterations, configuration 2")
+        p2 = w.make_problem(2)
+        c2 = rq.Circuit(p2.k, p2.pairs, param_of=p2.param_of)
+        t2 = rq.Target.from_dense(p2.U_ref, rq.RQ_C128)
+        rq.rq_tr_solve(c2, t2, p2.gates, max_iter=1)            # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, hist = rq.rq_tr_solve(c2, t2, p2.gates, max_iter=args.tr_iters)
+        dt = time.perf_counter() - t0
+        evals = int(1 + hist[:-1, 4].sum()) if len(hist) else 0
+        out["trust_region"] = {
+            "workload": "cfg2: k=12 Fermi-Hubbard target exp(-iH/2), 5-layer brick wall, "
+                        "30 Haar U(4) gates, 480 x 480 real Riemannian Hessian, c128",
+            "iterations": int(len(hist)), "seconds": round(dt, 3),
+            "ms_per_iteration": round(dt / max(1, len(hist)) * 1e3, 2),
+            "hessian_evaluations": evals,
+            "f": [round(float(v), 6) for v in hist[:, 0]],
+            "grad_norm": [float(f"{v:.4e}") for v in hist[:, 1]],
+            "accepted": [int(v) for v in hist[:, 4]]}
+        del t2
 
     if args.serving_requests > 0:
         del tgt64, tgt128

@@ -236,6 +236,36 @@ int rq_tr_step(int32_t n_params, uint32_t flags, const double *gates,
                const double *g, const double *H, double delta, double *eta,
                double *cand, double *model_decrease, int32_t *stop);
 
+/* Coordinates of matrices Y_p (host [P][4][4][2]) in the orthonormal tangent
+ * basis of rq_tangent_basis at the gates G_p: out[p*d + mu] =
+ * Re Tr[(G_p A_mu)^dagger Y_p] (host double[P*d]).  With Y the Euclidean
+ * gradient this is the Riemannian gradient vector taken by rq_tr_step (the
+ * projection onto the tangent space is orthogonal). */
+int rq_tangent_coords(int32_t n_params, uint32_t flags, const double *gates,
+                      const double *Y, double *out);
+
+/* Riemannian trust-region optimisation (Sec. "Riemannian optimization": the
+ * trust-region method of Absil et al., Algorithm 10, with the truncated-CG
+ * inner solver and the polar retraction of rq_tr_step).  Each iteration
+ * evaluates f, the gradient and the real Riemannian Hessian with
+ * rq_hess_blocks on the device (skipped after a rejected step, whose point
+ * is unchanged), takes rq_tr_step on the host, evaluates f at the candidate
+ * with rq_cost and accepts or shrinks with rq_tr_accept.  Radius: starts at
+ * delta_bar / 8 with delta_bar = sqrt(P*d) * pi.
+ * gates (host [P][4][4][2]): starting point on input, last accepted iterate on
+ * output.  Stops after max_iter iterations or when the Riemannian gradient
+ * norm is <= gtol.  history (host, nullable): double[max_iter][6] rows
+ * (f, |grad f|, delta, rho, accepted, tCG stop code) per iteration;
+ * *n_iter receives the number of rows written.
+ * exec: workspace of rq_tr_workspace_bytes(circuit, dtype, chunk) bytes; the
+ * call synchronizes exec->stream every iteration (host decisions). */
+size_t rq_tr_workspace_bytes(const rq_circuit *circuit, int32_t dtype,
+                             int64_t chunk);
+int rq_tr_solve(const rq_circuit *circuit, const rq_target *target,
+                double *gates, const rq_range *range, const rq_exec *exec,
+                int32_t max_iter, double gtol, double *history,
+                int32_t *n_iter);
+
 /* Trust-region acceptance and radius update after evaluating f at the
  * candidate: rho = (f0 - f1) / model_decrease; accepted = rho > 0.1; radius
  * quartered if rho < 1/4, doubled (capped at delta_bar) if rho > 3/4 and the

@@ -47,5 +47,5 @@ from .riemann import (  # noqa: F401
     tangent_from_real,
     polar,
 )
-from .trust_region import tcg, tr_step  # noqa: F401
+from .trust_region import tcg, tr_solve, tr_step  # noqa: F401
 from .evaluate import evaluate  # noqa: F401

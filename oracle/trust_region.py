@@ -81,3 +81,31 @@ def tr_step(gates: np.ndarray, f0: float, g: np.ndarray, H: np.ndarray, delta: f
     return dict(eta=eta, reason=reason, candidate=cand, f_candidate=f1, rho=rho,
                 accepted=accepted, new_delta=new_delta, model_decrease=model_dec,
                 gates=cand if accepted else gates)
+
+
+def tr_solve(gates: np.ndarray, evaluate_fn, cost_fn, max_iter: int, gtol: float = 0.0,
+             parity: bool = False):
+    """Riemannian trust-region method (Sec. "Riemannian optimization": the
+    method of Absil et al., Algorithm 10, with tCG as inner solver and the
+    polar retraction): repeat tr_step from the current point; the radius
+    starts at delta_bar / 8, delta_bar = sqrt(dim) * pi.
+
+    evaluate_fn(G) -> (f, g, H): cost, Riemannian gradient and Hessian in the
+    orthonormal tangent basis at G; cost_fn(G) -> f.
+    Returns (gates, history) with rows (f, |g|, delta, rho, accepted)."""
+    f, g, H = evaluate_fn(gates)
+    delta_bar = np.sqrt(g.size) * np.pi
+    delta = delta_bar / 8
+    hist = []
+    for _ in range(max_iter):
+        gn = float(np.linalg.norm(g))
+        if gn <= gtol:
+            hist.append((f, gn, delta, 0.0, False))
+            break
+        step = tr_step(gates, f, g, H, delta, cost_fn, parity=parity, delta_bar=delta_bar)
+        hist.append((f, gn, delta, step["rho"], step["accepted"]))
+        delta = step["new_delta"]
+        if step["accepted"]:
+            gates = step["candidate"]
+            f, g, H = evaluate_fn(gates)
+    return gates, hist

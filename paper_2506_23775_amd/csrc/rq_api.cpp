@@ -2,6 +2,7 @@
 // and the sweep schedule of rq_cost / rq_grad / rq_hvp / rq_apply_circuit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -886,6 +887,103 @@ size_t rq_hess_workspace_bytes(const rq_circuit *circuit, int32_t dtype, int64_t
   HessLayout H;
   if (make_hess_layout(circuit, dtype, chunk, H)) return 0;
   return H.total;
+}
+
+// Trust-region driver workspace: the Hessian workspace, then device outputs
+// f [1], egrad [P][4][4][2] and the real Hessian [P*d]^2.
+size_t rq_tr_workspace_bytes(const rq_circuit *circuit, int32_t dtype, int64_t chunk) {
+  HessLayout H;
+  if (make_hess_layout(circuit, dtype, chunk, H)) return 0;
+  const size_t n = size_t(H.P) * H.nd;
+  return align256(align256(align256(H.total) + 256) + size_t(H.P) * 32 * sizeof(double)) +
+         n * n * sizeof(double);
+}
+
+int rq_tr_solve(const rq_circuit *c, const rq_target *t, double *gates, const rq_range *range,
+                const rq_exec *ex, int32_t max_iter, double gtol, double *history,
+                int32_t *n_iter) {
+  if (n_iter) *n_iter = 0;
+  if (!t) return fail(RQ_EINVAL, "target is NULL");
+  if (!gates || max_iter < 0 || !(gtol >= 0)) return fail(RQ_EINVAL, "invalid gates / max_iter / gtol");
+  if (!ex || !ex->workspace) return fail(RQ_EINVAL, "exec or workspace is NULL");
+  HessLayout H;
+  int st = make_hess_layout(c, t ? t->dtype : -1, ex->chunk, H);
+  if (st) return st;
+  const size_t need = rq_tr_workspace_bytes(c, t->dtype, ex->chunk);
+  if (ex->workspace_bytes < need)
+    return fail(RQ_ESPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  const int P = H.P, d = H.nd, n = P * d;
+  const uint32_t flags = H.g.parity ? RQ_PARITY : 0u;
+  char *ws = static_cast<char *>(ex->workspace);
+  const size_t off_f = align256(H.total), off_eg = align256(off_f + 256),
+               off_hr = align256(off_eg + size_t(P) * 32 * sizeof(double));
+  double *d_f = reinterpret_cast<double *>(ws + off_f);
+  double *d_eg = reinterpret_cast<double *>(ws + off_eg);
+  double *d_hr = reinterpret_cast<double *>(ws + off_hr);
+  hipStream_t s = static_cast<hipStream_t>(ex->stream);
+  const rq_exec eh{ws, H.total, ex->chunk, ex->stream, 0u, 0u};
+
+  std::vector<double> G(gates, gates + size_t(P) * 32), cand(size_t(P) * 32), eg(size_t(P) * 32),
+      g(n), Hm(size_t(n) * n), eta(n);
+  const double delta_bar = std::sqrt(double(n)) * 3.14159265358979323846;
+  double delta = delta_bar / 8, f0 = 0.0, gnorm = 0.0;
+  bool evaluate = true;
+  int it = 0;
+  for (; it < max_iter; ++it) {
+    if (evaluate) {
+      st = run_hess(c, t, G.data(), range, &eh, d_f, d_eg, nullptr, nullptr, d_hr);
+      if (!st) st = hip_check(hipMemcpyAsync(&f0, d_f, sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+      if (!st)
+        st = hip_check(hipMemcpyAsync(eg.data(), d_eg, eg.size() * sizeof(double),
+                                      hipMemcpyDeviceToHost, s), "copy");
+      if (!st)
+        st = hip_check(hipMemcpyAsync(Hm.data(), d_hr, Hm.size() * sizeof(double),
+                                      hipMemcpyDeviceToHost, s), "copy");
+      if (!st) st = hip_check(hipStreamSynchronize(s), "synchronize");
+      if (st) return st;
+      rq_tangent_coords(P, flags, G.data(), eg.data(), g.data());
+      gnorm = 0.0;
+      for (double v : g) gnorm += v * v;
+      gnorm = std::sqrt(gnorm);
+    }
+    double *row = history ? history + size_t(it) * 6 : nullptr;
+    if (row) {
+      row[0] = f0;
+      row[1] = gnorm;
+      row[2] = delta;
+      row[3] = 0.0;
+      row[4] = 0.0;
+      row[5] = -1.0;
+    }
+    if (gnorm <= gtol) {
+      ++it;
+      break;
+    }
+    double md = 0.0, nd = 0.0, rho = 0.0, f1 = 0.0;
+    int32_t stop = 0, acc = 0;
+    st = rq_tr_step(P, flags, G.data(), g.data(), Hm.data(), delta, eta.data(), cand.data(), &md,
+                    &stop);
+    if (st) return fail(st, "trust-region step failed");
+    st = run_sweep(c, t, cand.data(), nullptr, range, &eh, RQ_OP_COST, d_f, nullptr, nullptr,
+                   nullptr, nullptr);
+    if (!st) st = hip_check(hipMemcpyAsync(&f1, d_f, sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    if (!st) st = hip_check(hipStreamSynchronize(s), "synchronize");
+    if (st) return st;
+    double en = 0.0;
+    for (double v : eta) en += v * v;
+    rq_tr_accept(f0, f1, md, delta, delta_bar, std::sqrt(en), &nd, &acc, &rho);
+    if (row) {
+      row[3] = rho;
+      row[4] = acc ? 1.0 : 0.0;
+      row[5] = stop;
+    }
+    if (acc) G = cand;
+    evaluate = acc != 0;
+    delta = nd;
+  }
+  std::copy(G.begin(), G.end(), gates);
+  if (n_iter) *n_iter = it;
+  return RQ_OK;
 }
 
 int rq_hess_blocks(const rq_circuit *circuit, const rq_target *target, const double *gates,

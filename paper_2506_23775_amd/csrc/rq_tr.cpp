@@ -221,6 +221,32 @@ int rq_tr_step(int32_t n_params, uint32_t flags, const double *gates, const doub
   return RQ_OK;
 }
 
+int rq_tangent_coords(int32_t n_params, uint32_t flags, const double *gates, const double *Y,
+                      double *out) {
+  if (n_params < 1 || !gates || !Y || !out) return RQ_EINVAL;
+  std::vector<cd> B;
+  const int d = basis((flags & RQ_PARITY) != 0, B);
+  for (int p = 0; p < n_params; ++p) {
+    cd G[16], Yp[16];
+    for (int i = 0; i < 16; ++i) {
+      G[i] = cd(gates[(size_t(p) * 16 + i) * 2], gates[(size_t(p) * 16 + i) * 2 + 1]);
+      Yp[i] = cd(Y[(size_t(p) * 16 + i) * 2], Y[(size_t(p) * 16 + i) * 2 + 1]);
+    }
+    for (int m = 0; m < d; ++m) {
+      // <G A_m, Y> = Re sum_ab conj((G A_m)_ab) Y_ab
+      double s = 0.0;
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          cd x = 0.0;
+          for (int c = 0; c < 4; ++c) x += G[4 * a + c] * B[size_t(m) * 16 + 4 * c + b];
+          s += (std::conj(x) * Yp[4 * a + b]).real();
+        }
+      out[size_t(p) * d + m] = s;
+    }
+  }
+  return RQ_OK;
+}
+
 int rq_tr_accept(double f0, double f1, double model_decrease, double delta, double delta_bar,
                  double eta_norm, double *new_delta, int32_t *accepted, double *rho) {
   if (!new_delta || !accepted) return RQ_EINVAL;

@@ -59,6 +59,7 @@ _lib = None
 
 EXPORTS = ["rq_workspace_bytes", "rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks",
            "rq_hess_workspace_bytes", "rq_apply_circuit", "rq_tr_step", "rq_tr_accept",
+           "rq_tangent_coords", "rq_tr_workspace_bytes", "rq_tr_solve",
            "rq_tangent_basis", "rq_plan_passes", "rq_profile_enable", "rq_profile_read",
            "rq_strerror", "rq_last_error"]
 
@@ -90,6 +91,12 @@ def lib():
     L.rq_tr_accept.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                C.c_double, dp, C.POINTER(C.c_int32), dp]
     L.rq_tangent_basis.argtypes = [C.c_uint32, dp]
+    L.rq_tangent_coords.argtypes = [C.c_int32, C.c_uint32, dp, dp, dp]
+    L.rq_tr_workspace_bytes.restype = C.c_size_t
+    L.rq_tr_workspace_bytes.argtypes = [C.POINTER(_Circuit), C.c_int32, C.c_int64]
+    L.rq_tr_solve.argtypes = [C.POINTER(_Circuit), C.POINTER(_Target), dp, C.POINTER(_Range),
+                              C.POINTER(_Exec), C.c_int32, C.c_double, dp,
+                              C.POINTER(C.c_int32)]
     L.rq_plan_passes.argtypes = [C.POINTER(_Circuit), C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     L.rq_profile_enable.argtypes = [C.c_int]
     L.rq_profile_read.argtypes = [dp, C.POINTER(C.c_int64), dp, dp]
@@ -97,6 +104,7 @@ def lib():
     L.rq_last_error.restype = C.c_char_p
     for name in ["rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks", "rq_apply_circuit",
                  "rq_tr_step", "rq_tr_accept", "rq_tangent_basis", "rq_plan_passes",
+                 "rq_tangent_coords", "rq_tr_solve",
                  "rq_profile_enable", "rq_profile_read"]:
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -445,6 +453,40 @@ def rq_tr_accept(f0, f1, model_decrease, delta, delta_bar, eta_norm):
     _check(lib().rq_tr_accept(f0, f1, model_decrease, delta, delta_bar, eta_norm, C.byref(nd),
                               C.byref(acc), C.byref(rho)), "rq_tr_accept")
     return nd.value, bool(acc.value), rho.value
+
+
+def rq_tangent_coords(gates, Y, parity: bool = False) -> np.ndarray:
+    """Coordinates Re Tr[(G_p A_mu)^dagger Y_p] in the tangent basis (host)."""
+    G = _gates_host(gates)
+    Yh = _gates_host(Y)
+    d = 8 if parity else 16
+    out = np.zeros(G.shape[0] * d)
+    _check(lib().rq_tangent_coords(G.shape[0], RQ_PARITY if parity else 0, _dptr(G), _dptr(Yh),
+                                   _dptr(out)), "rq_tangent_coords")
+    return out
+
+
+def rq_tr_solve(circuit: Circuit, target: Target, gates, max_iter: int = 20, gtol: float = 0.0,
+                range=None, chunk=None, workspace=None, stream=None):
+    """Riemannian trust-region optimisation on the device (rq_tr_solve).
+    Returns (gates [P,4,4] complex128 host, history [n_iter, 6]: f, |grad|,
+    delta, rho, accepted, tCG stop code)."""
+    G = _gates_host(gates).copy()
+    L = lib()
+    if chunk is None:
+        chunk = default_chunk(circuit, RQ_OP_HESS, target.dtype, circuit.ncols)
+    need = L.rq_tr_workspace_bytes(C.byref(circuit._c), target.dtype, chunk)
+    if need == 0:
+        raise RQError(RQ_EINVAL, "rq_tr_workspace_bytes")
+    ws = workspace if workspace is not None else _workspace(need, key=("tr",))
+    s = stream if stream is not None else torch.cuda.current_stream()
+    ex = _Exec(ws.ptr, ws.nbytes, chunk, s.cuda_stream)
+    hist = np.zeros((max(1, max_iter), 6))
+    n = C.c_int32(0)
+    t = target.struct()
+    _check(L.rq_tr_solve(C.byref(circuit._c), C.byref(t), _dptr(G), _range(range), C.byref(ex),
+                         int(max_iter), float(gtol), _dptr(hist), C.byref(n)), "rq_tr_solve")
+    return G, hist[:n.value]
 
 
 def build_trotter_target(k: int, gate_list, dtype: int = RQ_C128, parity: bool = True,

@@ -166,3 +166,34 @@ def test_tr_accept_rule(rq):
     assert nd == 2.0 and acc
     nd, acc, rho = rq.rq_tr_accept(1.0, 0.5, 0.5, 1.0, 10.0, 0.3)
     assert nd == 1.0 and acc
+
+
+@pytest.mark.parametrize("parity", [False, True])
+def test_tangent_coords_vs_oracle(rq, parity):
+    """rq_tangent_coords (host) against the oracle's tangent coordinates of
+    the Euclidean gradient."""
+    rng = np.random.default_rng([61, parity])
+    P = 5
+    G = (w.parity_haar_gates if parity else w.haar_gates)(rng, P)
+    Y = rng.standard_normal((P, 4, 4)) + 1j * rng.standard_normal((P, 4, 4))
+    if parity:
+        Y = np.where(O.riemann.PARITY_MASK, Y, 0)
+    got = rq.rq_tangent_coords(G, Y, parity=parity)
+    ref = O.gradient_real(G, Y, parity)
+    assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_tr_solve_rejects_bad_arguments(rq):
+    circ = rq.Circuit(4, [(0, 1), (2, 3)])
+    t = rq._Target(rq.RQ_C128, 0, 8, 16, 0, None, 0, 0)
+    ex = rq._Exec(256, 1 << 20, 64, None, 0, 0)
+    G = np.stack([np.eye(4, dtype=complex)] * 2)
+    n = C.c_int32(0)
+    L = rq.lib()
+    st = L.rq_tr_solve(C.byref(circ._c), C.byref(t), rq._dptr(G), None, C.byref(ex), -1, 0.0,
+                       None, C.byref(n))
+    assert st == rq.RQ_EINVAL
+    st = L.rq_tr_solve(C.byref(circ._c), C.byref(t), rq._dptr(G), None, C.byref(ex), 3, 0.0,
+                       None, C.byref(n))
+    assert st == rq.RQ_ESPACE          # 1 MiB is below rq_tr_workspace_bytes
+    assert L.rq_tr_workspace_bytes(C.byref(circ._c), rq.RQ_C128, 64) > (1 << 20)
