@@ -82,7 +82,18 @@ extern "C" {
  * pairs:    [n_gates][2] (q_hi, q_lo), 0 <= q < n_qubits, q_hi != q_lo.
  * param_of: [n_gates] parameter of each instance in [0, n_params), or NULL
  *           for the identity map (then n_params must equal n_gates).
- * n_qubits: 2..30 (4..31 with RQ_PARITY). */
+ * n_qubits: 2..30 (4..31 with RQ_PARITY).
+ * shift:    0, or s in [1, n_qubits): the caller states that the circuit and
+ *           the target are invariant under the cyclic qubit translation
+ *           q -> (q + s) mod n_qubits (Sec. "Exploiting translational
+ *           invariance").  The library checks the circuit part -- every
+ *           instance maps to an instance of the same parameter on the shifted
+ *           pair, in the same order on every qubit -- and rejects the circuit
+ *           otherwise (RQ_EINVAL); the target's invariance is the caller's
+ *           promise.  rq_hess_blocks then sweeps only the gate holes needed
+ *           for one pair of each translation class over the full trace and
+ *           fills the others by translation.  Ignored for basis sub-ranges
+ *           and input states (their sums are not translation invariant). */
 typedef struct rq_circuit {
   int32_t n_qubits;
   int32_t n_gates;
@@ -90,6 +101,8 @@ typedef struct rq_circuit {
   uint32_t flags;
   const int32_t *pairs;
   const int32_t *param_of;
+  int32_t shift;
+  int32_t reserved;
 } rq_circuit;
 
 /* Target U given by its columns U|j> on the device (Sec. "Objective function

@@ -39,10 +39,13 @@ int launch_onehot(int is_double, void *dst, int64_t rows, int64_t ld, int64_t co
                   void *s);
 int launch_accum_rows(const double *slots, int rows, int nslots, double *acc, void *s);
 int launch_hess_post(int N, int P, int d, const double *hh, const int32_t *inst_off,
-                     const int32_t *inst_list, const int32_t *ppos, const double *gates64,
+                     const int32_t *inst_list, const int32_t *ppos, const int32_t *map,
+                     const double *gates64,
                      const double *egrad,
                      const double *basis, double *hess_holo, double *hess_real, void *s);
-constexpr int kHessSlots = 256;
+// FP64 partial-sum slots (one per wavefront) of the Hessian sweeps: 2048
+// wavefronts, two per SIMD.
+constexpr int kHessSlots = 2048;
 }  // namespace rqk
 
 namespace {
@@ -101,6 +104,41 @@ int entries(int op, bool parity) {
   return 0;
 }
 
+int param_of(const rq_circuit *c, int g) { return c->param_of ? c->param_of[g] : g; }
+
+// Instance permutation tau of the cyclic qubit translation by c->shift:
+// tau[l] is the instance on the shifted pair (same orientation, same
+// parameter), and on every qubit q the instances touching q map in order onto
+// those touching q + shift, so the translation maps the circuit's gate graph
+// onto itself.  Fails (RQ_EINVAL) if the circuit is not invariant.
+int translation_map(const rq_circuit *c, std::vector<int> &tau) {
+  const int N = c->n_gates, k = c->n_qubits, s = c->shift;
+  std::vector<std::vector<int>> on(k);
+  for (int l = 0; l < N; ++l) {
+    on[c->pairs[2 * l]].push_back(l);
+    on[c->pairs[2 * l + 1]].push_back(l);
+  }
+  tau.assign(N, -1);
+  for (int q = 0; q < k; ++q) {
+    const std::vector<int> &a = on[q], &b = on[(q + s) % k];
+    if (a.size() != b.size()) return fail(RQ_EINVAL, "circuit is not invariant under the shift");
+    for (size_t i = 0; i < a.size(); ++i) {
+      const int l = a[i], m = b[i];
+      if (tau[l] != -1 && tau[l] != m) return fail(RQ_EINVAL, "circuit is not invariant under the shift");
+      tau[l] = m;
+    }
+  }
+  std::vector<char> hit(N, 0);
+  for (int l = 0; l < N; ++l) {
+    const int m = tau[l];
+    if (m < 0 || hit[m] || c->pairs[2 * m] != (c->pairs[2 * l] + s) % k ||
+        c->pairs[2 * m + 1] != (c->pairs[2 * l + 1] + s) % k || param_of(c, m) != param_of(c, l))
+      return fail(RQ_EINVAL, "circuit is not invariant under the shift");
+    hit[m] = 1;
+  }
+  return RQ_OK;
+}
+
 int check_circuit(const rq_circuit *c) {
   if (!c) return fail(RQ_EINVAL, "circuit is NULL");
   const bool parity = c->flags & RQ_PARITY;
@@ -123,10 +161,14 @@ int check_circuit(const rq_circuit *c) {
         return fail(RQ_EINVAL, "gate " + std::to_string(g) + ": param_of out of range");
     }
   }
+  if (c->shift < 0 || c->shift >= c->n_qubits) return fail(RQ_EINVAL, "shift out of range");
+  if (c->shift) {
+    std::vector<int> tau;
+    return translation_map(c, tau);
+  }
   return RQ_OK;
 }
 
-int param_of(const rq_circuit *c, int g) { return c->param_of ? c->param_of[g] : g; }
 
 struct Layout {
   int op = 0, is_double = 0, parity = 0, kq = 0, nt = 0, ne = 0, nbuf = 0;
@@ -614,7 +656,7 @@ struct HessLayout {
   size_t esize = 0, slab_bytes = 0;
   int64_t rows = 0, chunk = 0;
   size_t off_coef = 0, off_coefT = 0, off_g64 = 0, off_basis = 0, off_ioff = 0, off_ilist = 0,
-         off_ppos = 0,
+         off_ppos = 0, off_map = 0,
          upload_end = 0, off_f = 0, off_eg = 0, off_rg = 0, off_hh = 0, off_slots = 0,
          off_psi = 0, off_phi = 0, off_arr = 0, total = 0;
 };
@@ -649,6 +691,8 @@ int make_hess_layout(const rq_circuit *c, int32_t dtype, int64_t chunk, HessLayo
   o = align256(o + size_t(H.N) * sizeof(int32_t));
   H.off_ppos = o;
   o = align256(o + size_t(H.N) * sizeof(int32_t));
+  H.off_map = o;
+  o = align256(o + size_t(H.N) * H.N * sizeof(int32_t));
   H.upload_end = o;
   H.off_f = o;
   o = align256(o + sizeof(double));
@@ -717,6 +761,67 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
       ppos[g] = (int)order.size();
       order.push_back(g);
     }
+  // Gate holes to sweep, and for every instance pair (l, m) with l before m
+  // along pi the stored block its Hessian block is read from: map[l*N+m] =
+  // a*N+b (block of hole a at gate b, a before b) or -(a*N+b)-1 for the
+  // transposed block.  With a translation symmetry and the full trace, pairs
+  // related by the translation have equal blocks (Sec. "Exploiting
+  // translational invariance"), so holes are swept greedily along pi until
+  // every translation class of pairs has a computed member; otherwise every
+  // hole is swept and map is the identity.
+  std::vector<char> sweep(N, 1);
+  std::vector<int32_t> map(size_t(N) * N);
+  for (int l = 0; l < N; ++l)
+    for (int m = 0; m < N; ++m) map[size_t(l) * N + m] = l * N + m;
+  const bool full_trace = R.begin == 0 && R.count == (int64_t(1) << L.kq);
+  if (c->shift && full_trace && !t->inputs) {
+    std::vector<int> tau;
+    st = translation_map(c, tau);
+    if (st) return st;
+    std::vector<std::vector<int>> grp(1, std::vector<int>(N));
+    for (int l = 0; l < N; ++l) grp[0][l] = l;
+    for (;;) {
+      std::vector<int> nx(N);
+      for (int l = 0; l < N; ++l) nx[l] = tau[grp.back()[l]];
+      if (nx == grp[0]) break;
+      grp.push_back(nx);
+    }
+    auto key = [&](int l, int m) {
+      int best = N * N;
+      for (const auto &g : grp) {
+        const int a = std::min(g[l], g[m]), b = std::max(g[l], g[m]);
+        best = std::min(best, a * N + b);
+      }
+      return best;
+    };
+    std::vector<char> covered(size_t(N) * N, 0);
+    std::fill(sweep.begin(), sweep.end(), 0);
+    for (int u = 0; u + 1 < N; ++u) {
+      const int a = order[u];
+      bool need = false;
+      for (int v = u + 1; v < N && !need; ++v) need = !covered[key(a, order[v])];
+      if (!need) continue;
+      sweep[a] = 1;
+      for (int v = u + 1; v < N; ++v) covered[key(a, order[v])] = 1;
+    }
+    for (int l = 0; l < N; ++l)
+      for (int m = 0; m < N; ++m) {
+        if (ppos[l] >= ppos[m]) continue;
+        bool found = false;
+        for (const auto &g : grp) {
+          const int a = g[l], b = g[m];
+          if (sweep[a] && ppos[a] < ppos[b]) {
+            map[size_t(l) * N + m] = a * N + b;
+            found = true;
+          } else if (sweep[b] && ppos[b] < ppos[a]) {
+            map[size_t(l) * N + m] = -(b * N + a) - 1;
+            found = true;
+          }
+          if (found) break;
+        }
+        if (!found) return fail(RQ_EHIP, "internal: a translation class of hole pairs is not covered");
+      }
+  }
   std::vector<PlanPass> single(N);
   for (int g = 0; g < N; ++g) {
     std::vector<PlanPass> pp;
@@ -759,6 +864,7 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
     ioff[P] = pos;
     int32_t *pp = reinterpret_cast<int32_t *>(hs.data() + (H.off_ppos - L.total));
     for (int l = 0; l < N; ++l) pp[l] = ppos[l];
+    std::memcpy(hs.data() + (H.off_map - L.total), map.data(), map.size() * sizeof(int32_t));
   }
   st = hip_check(hipMemcpyAsync(ws + L.total, hs.data(), hs.size(), hipMemcpyHostToDevice, s),
                  "upload");
@@ -843,6 +949,7 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
       const int rows_all = N * H.nd * H.ne;
       for (int t = 0; t + 1 < N; ++t) {
         const int h = order[t];
+        if (!sweep[h]) continue;
         const int qh = c->pairs[2 * h], ql = c->pairs[2 * h + 1];
         if (launch_hole(L.is_double, slab(psi, t), arr, H.rows, H.chunk, ncols, H.nd, c->n_qubits,
                         qh, ql, L.parity, sector, s))
@@ -868,7 +975,8 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
   const int32_t *ioff = reinterpret_cast<const int32_t *>(ws + H.off_ioff);
   const int32_t *il = reinterpret_cast<const int32_t *>(ws + H.off_ilist);
   const int32_t *ppd = reinterpret_cast<const int32_t *>(ws + H.off_ppos);
-  if (launch_hess_post(N, P, H.nd, hh, ioff, il, ppd, reinterpret_cast<const double *>(ws + H.off_g64),
+  const int32_t *mapd = reinterpret_cast<const int32_t *>(ws + H.off_map);
+  if (launch_hess_post(N, P, H.nd, hh, ioff, il, ppd, mapd, reinterpret_cast<const double *>(ws + H.off_g64),
                        eg_int, reinterpret_cast<const double *>(ws + H.off_basis), d_hh, d_hr, s))
     return fail(RQ_EHIP, "Hessian assembly launch failed");
   if (d_f) st = hip_check(hipMemcpyAsync(d_f, f_int, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");

@@ -255,7 +255,7 @@ __device__ inline zc zmul(zc a, zc b) { return {a.x * b.x - a.y * b.y, a.x * b.y
 __global__ __launch_bounds__(256) void k_hess_post(
     int N, int P, int d, const double *__restrict__ hh, const int32_t *__restrict__ inst_off,
     const int32_t *__restrict__ inst_list, const int32_t *__restrict__ ppos,
-    const double *__restrict__ gates64,
+    const int32_t *__restrict__ map, const double *__restrict__ gates64,
     const double *__restrict__ egrad, const double *__restrict__ basis, double *hess_holo,
     double *hess_real) {
   const int p = blockIdx.x / P, q = blockIdx.x % P;
@@ -265,6 +265,14 @@ __global__ __launch_bounds__(256) void k_hess_post(
   // entry index e -> row-major 4x4 position
   const int pidx[8] = {0, 3, 12, 15, 5, 6, 9, 10};
   auto epos = [&](int e) { return d == 8 ? pidx[e] : e; };
+  // entry (r, c) of the block of instance pair (l, m), l before m along the
+  // sweep order: a stored block, or the transpose of one (translation classes)
+  auto blk = [&](int l, int m, int r, int c) -> const double * {
+    const int32_t v = map[int64_t(l) * N + m];
+    if (v >= 0) return hh + ((int64_t(v) * d + r) * 2 * d + 2 * c);
+    const int64_t w = -int64_t(v) - 1;
+    return hh + ((w * d + c) * 2 * d + 2 * r);
+  };
   if (t < d * d) {
     const int e = t / d, f = t % d;
     double sx = 0, sy = 0;
@@ -272,7 +280,7 @@ __global__ __launch_bounds__(256) void k_hess_post(
       for (int j = inst_off[q]; j < inst_off[q + 1]; ++j) {
         const int l = inst_list[i], m = inst_list[j];
         if (ppos[l] < ppos[m]) {
-          const double *h = hh + ((int64_t(l) * N + m) * d + e) * 2 * d + 2 * f;
+          const double *h = blk(l, m, e, f);
           sx += h[0];
           sy += h[1];
         }
@@ -281,7 +289,7 @@ __global__ __launch_bounds__(256) void k_hess_post(
       for (int j = inst_off[p]; j < inst_off[p + 1]; ++j) {
         const int l = inst_list[i], m = inst_list[j];
         if (ppos[l] < ppos[m]) {
-          const double *h = hh + ((int64_t(l) * N + m) * d + f) * 2 * d + 2 * e;
+          const double *h = blk(l, m, f, e);
           sx += h[0];
           sy += h[1];
         }
@@ -437,11 +445,13 @@ int launch_accum_rows(const double *slots, int rows, int nslots, double *acc, vo
 }
 
 int launch_hess_post(int N, int P, int d, const double *hh, const int32_t *inst_off,
-                     const int32_t *inst_list, const int32_t *ppos, const double *gates64,
+                     const int32_t *inst_list, const int32_t *ppos, const int32_t *map,
+                     const double *gates64,
                      const double *egrad, const double *basis, double *hess_holo,
                      double *hess_real, void *s) {
   hipLaunchKernelGGL(k_hess_post, dim3(P * P), dim3(256), 0, (hipStream_t)s, N, P, d, hh,
-                     inst_off, inst_list, ppos, gates64, egrad, basis, hess_holo, hess_real);
+                     inst_off, inst_list, ppos, map, gates64, egrad, basis, hess_holo,
+                     hess_real);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

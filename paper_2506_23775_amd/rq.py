@@ -33,7 +33,8 @@ RQ_OP_COST, RQ_OP_GRAD, RQ_OP_HVP, RQ_OP_HESS, RQ_OP_APPLY = 0, 1, 2, 3, 4
 class _Circuit(C.Structure):
     _fields_ = [("n_qubits", C.c_int32), ("n_gates", C.c_int32), ("n_params", C.c_int32),
                 ("flags", C.c_uint32), ("pairs", C.POINTER(C.c_int32)),
-                ("param_of", C.POINTER(C.c_int32))]
+                ("param_of", C.POINTER(C.c_int32)), ("shift", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class _Target(C.Structure):
@@ -142,7 +143,7 @@ class Circuit:
     """Gate topology: k qubits, pairs [(q_hi, q_lo)], optional param_of."""
 
     def __init__(self, k: int, pairs: Sequence, param_of=None, n_params: Optional[int] = None,
-                 parity: bool = False):
+                 parity: bool = False, shift: int = 0):
         self.k = int(k)
         self.pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
         self.n_gates = self.pairs.shape[0]
@@ -153,10 +154,12 @@ class Circuit:
             self.param_of = np.ascontiguousarray(np.asarray(param_of, dtype=np.int32))
             self.n_params = int(self.param_of.max()) + 1 if n_params is None else int(n_params)
         self.parity = bool(parity)
+        self.shift = int(shift)   # translation symmetry (qubits), 0: none
         self._c = _Circuit(self.k, self.n_gates, self.n_params, RQ_PARITY if parity else 0,
                            self.pairs.ctypes.data_as(C.POINTER(C.c_int32)),
                            None if self.param_of is None
-                           else self.param_of.ctypes.data_as(C.POINTER(C.c_int32)))
+                           else self.param_of.ctypes.data_as(C.POINTER(C.c_int32)),
+                           self.shift, 0)
 
     @property
     def kq(self):

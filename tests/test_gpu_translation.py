@@ -1,0 +1,100 @@
+"""rq_hess_blocks with a declared translation symmetry (only translation-
+unique hole pairs swept, Sec. "Exploiting translational invariance") against
+the same call without it and against the oracle; sub-ranges and input states
+ignore the symmetry."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as w
+from gpu_helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 2e-6}
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import torch
+    from paper_2506_23775_amd import rq as _rq
+    assert torch.cuda.is_available()
+    _rq.lib()
+    return _rq
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _hess(rq, k, pairs, layer, gates, tgt, parity, shift, **kw):
+    circ = rq.Circuit(k, pairs, param_of=layer, parity=parity, shift=shift)
+    return [None if x is None else _np(x) for x in rq.rq_hess_blocks(circ, tgt, gates, **kw)]
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("case", ["parity_exact", "dense_exact", "parity_trotter"])
+def test_shift_equals_full_hole_set(rq, dtype, case):
+    rng = np.random.default_rng([101, dtype, len(case)])
+    k = 8
+    parity = case.startswith("parity")
+    layers = 5 if parity else 4
+    pairs, layer = w.brickwall_pairs(k, layers)
+    gates = (w.parity_haar_gates if parity else w.haar_gates)(rng, layers)
+    if case.endswith("trotter"):
+        gl = w.strang_trotter_gates(4, 0.5, 4, 1.0, 4.0)
+        tgt = rq.build_trotter_target(k, gl, dtype=dtype, parity=True)
+        shift = 4
+    else:
+        tgt = rq.Target.from_dense(w.target_unitary(4, 0.5, 1.0, 4.0), dtype, parity=parity)
+        shift = 2
+    a = _hess(rq, k, pairs, layer, gates, tgt, parity, 0, chunk=64)
+    b = _hess(rq, k, pairs, layer, gates, tgt, parity, shift, chunk=64)
+    for x, y in zip(a, b):
+        assert rel(y, x) <= TOL[dtype], rel(y, x)
+
+
+def test_shift_against_oracle(rq):
+    rng = np.random.default_rng(102)
+    k = 6
+    pairs, layer = w.brickwall_pairs(k, 3)
+    layer = np.asarray(layer)
+    gates = w.parity_haar_gates(rng, 3)
+    U = w.target_unitary(3, 0.5, 1.0, 4.0)
+    tgt = rq.Target.from_dense(U, rq.RQ_C128, parity=True)
+    _, eg, _, hh, hr = _hess(rq, k, pairs, layer, gates, tgt, True, 2, chunk=64)
+    inst = gates[layer]
+    Hi = O.hessian_holomorphic(k, pairs, inst, U, mask=O.riemann.PARITY_MASK)
+    P, N = 3, len(pairs)
+    Hp = np.zeros((P, 4, 4, P, 4, 4), dtype=complex)
+    for l in range(N):
+        for m in range(N):
+            Hp[layer[l], :, :, layer[m]] += Hi[l, :, :, m]
+    pidx = [0, 3, 12, 15, 5, 6, 9, 10]
+    Hh = Hp.reshape(P, 16, P, 16)[:, pidx][:, :, :, pidx]
+    assert rel(hh, Hh) <= 1e-10
+    T = np.where(O.riemann.PARITY_MASK, O.per_param(O.euclidean_T(k, pairs, inst, U), layer, P), 0)
+    assert rel(hr, O.hessian_real(gates, O.egrad(T), Hp, True)) <= 1e-10
+
+
+def test_shift_ignored_for_subrange_and_inputs(rq):
+    import torch
+    rng = np.random.default_rng(103)
+    k = 8
+    pairs, layer = w.brickwall_pairs(k, 3)
+    gates = w.parity_haar_gates(rng, 3)
+    U = w.target_unitary(4, 0.5, 1.0, 4.0)
+    tgt = rq.Target.from_dense(U, rq.RQ_C128, parity=True)
+    a = _hess(rq, k, pairs, layer, gates, tgt, True, 0, range=(1, 7, 90), chunk=64)
+    b = _hess(rq, k, pairs, layer, gates, tgt, True, 2, range=(1, 7, 90), chunk=64)
+    for x, y in zip(a, b):
+        assert rel(y, x) <= 1e-13
+    Z = torch.from_numpy(w.random_states(rng, 1 << (k - 1), 2 * 20).reshape(-1, 2, 20)
+                         .transpose(1, 0, 2).copy()).cuda()
+    ref = torch.stack([tgt.ref[p] @ Z[p] for p in (0, 1)]).contiguous()
+    ti = rq.Target(ref, rq.RQ_C128, True, inputs=Z.contiguous())
+    a = _hess(rq, k, pairs, layer, gates, ti, True, 0, range=(-1, 0, 20), chunk=64)
+    b = _hess(rq, k, pairs, layer, gates, ti, True, 2, range=(-1, 0, 20), chunk=64)
+    for x, y in zip(a, b):
+        assert rel(y, x) <= 1e-13
