@@ -66,6 +66,12 @@ def gpu_run(rq, torch, circ, target, prob, steps, warmup, chunk, basis_range=Non
     return dict(seconds=t1 - t0, lat_ms=lat, prof=prof, result=res, ws_bytes=ws_need)
 
 
+def _kernel_name(key):
+    names = {("hess", "sweep"): "k_hess_pass", ("hess", "states"): "k_pass (per-gate states)",
+             ("hess", "hole"): "k_hole"}
+    return names.get(key, f"k_pass {key[0]}/{key[1]}")
+
+
 def roofline(prof, key):
     st = prof[key]
     n = st["launches"]
@@ -79,12 +85,12 @@ def roofline(prof, key):
     if hbm_frac >= alu_frac:
         return dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(hbm_frac, 4), traffic=None,
-                    kernel=f"k_pass {key[0]}/{key[1]}", avg_launch_ms=round(avg_s * 1e3, 4),
+                    kernel=_kernel_name(key), avg_launch_ms=round(avg_s * 1e3, 4),
                     alu=dict(achieved=round(tfl, 2), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
                              frac=round(alu_frac, 4)))
     return dict(bound="alu", achieved=round(tfl, 2), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
                 frac=round(alu_frac, 4), traffic=None,
-                kernel=f"k_pass {key[0]}/{key[1]}", avg_launch_ms=round(avg_s * 1e3, 4),
+                kernel=_kernel_name(key), avg_launch_ms=round(avg_s * 1e3, 4),
                 hbm=dict(achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                          frac=round(hbm_frac, 4)))
 
@@ -188,6 +194,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sampled-vectors", type=int, default=256,
                     help="random vectors per parity sector in the sampled-trace leg (0: skip)")
+    ap.add_argument("--hessian", type=int, default=1,
+                    help="1: time the configuration-3 Hessian blocks (0: skip)")
     ap.add_argument("--tr-iters", type=int, default=5,
                     help="trust-region iterations in the configuration-2 leg (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=16,
@@ -256,6 +264,36 @@ def main():
     out["roofline"] = roofline(r64["prof"], dom)
     if args.chunk == 4096:
         out["roofline"]["traffic"] = measured_traffic(f"{dom[0]}/{dom[1]}")
+
+    if args.hessian:
+        # all pairwise Hessian blocks of configuration 3 over the full trace,
+        # with the two-site translation symmetry of the brick wall and the
+        # Strang target (only translation-unique hole pairs swept)
+        log("[bench] Hessian leg: configuration 3, shift 4")
+        c3s = rq.Circuit(prob.k, prob.pairs, param_of=prob.param_of, parity=True, shift=4)
+        torch.cuda.synchronize()
+        rq.rq_profile_read()
+        rq.rq_profile_enable(True)
+        t0 = time.perf_counter()
+        hres = rq.rq_hess_blocks(c3s, tgt64, prob.gates, chunk=1024)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rq.rq_profile_enable(False)
+        hprof = rq.rq_profile_read()
+        hr = hres[4].cpu().numpy()
+        hdom = max(hprof.items(), key=lambda kv: kv[1]["ms"])[0]
+        out["hessian"] = {
+            "workload": "cfg3 Hessian: 56 x 56 instance blocks (7 x 7 parameter blocks of 8 x 8 "
+                        "complex entries, 56 x 56 real Riemannian Hessian) over 2 x 2^15 basis "
+                        "states, c64 + FP64 accumulation, translation-unique hole pairs (shift 4)",
+            "seconds": round(dt, 3),
+            "kernels": {f"{k[0]}/{k[1]}": dict(ms=round(v["ms"], 1), launches=v["launches"],
+                                               GBps=round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1),
+                                               TFLOPs=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2))
+                        for k, v in hprof.items()},
+            "roofline": roofline(hprof, hdom),
+            "symmetric_rel": float(f"{np.abs(hr - hr.T).max() / np.abs(hr).max():.2e}")}
+        log(f"[bench] Hessian: {dt:.2f} s")
 
     if args.sampled_vectors > 0:
         # trace over random vectors instead of the 2^16 basis states (same

@@ -300,10 +300,12 @@ int rq_plan_passes(const rq_circuit *circuit, int32_t op, int32_t dtype,
 /* Diagnostics: with profiling enabled, every sweep-kernel launch is
  * bracketed by HIP events recorded on the launch's own stream.
  * rq_profile_read synchronizes those events and returns, per kind
- * k = 3*op + stage (op: 0 cost, 1 grad, 2 HVP, 3 apply; stage: 0 forward
- * pass, 1 fused last pass, 2 backward pass), the summed kernel time in ms,
- * the number of launches, and the algorithmic HBM bytes and flops of those
- * launches (arrays of 12 entries each, any may be NULL); then it resets. */
+ * k = 3*op + stage for k < 12 (op: 0 cost, 1 grad, 2 HVP, 3 apply; stage:
+ * 0 forward pass, 1 fused last pass, 2 backward pass), and k = 12 Hessian
+ * hole-array sweep, 13 Hessian per-gate state passes, 14 gate-hole
+ * application, the summed kernel time in ms, the number of launches, and the
+ * algorithmic HBM bytes and flops of those launches (arrays of 15 entries
+ * each, any may be NULL); then it resets. */
 int rq_profile_enable(int on);
 int rq_profile_read(double *ms, int64_t *launches, double *bytes,
                     double *flops);

@@ -416,8 +416,11 @@ double flops_per_amp_gate(int op, int stage, bool parity) {
   return s * (fwd + bwd);
 }
 
-int launch_prof(int is_double, int nt, int parity, int op, int stage, const PassArgs &a, int grid,
-                hipStream_t s, double slabs) {
+// Profiled launch: HIP events around launch() on stream s when profiling is
+// on; kind, algorithmic bytes and flops are recorded with the events.
+constexpr int kProfKinds = 15;
+template <typename F>
+int prof_launch(hipStream_t s, int kind, double bytes, double flops, F &&launch) {
   ProfRec r{};
   bool on;
   {
@@ -429,18 +432,25 @@ int launch_prof(int is_double, int nt, int parity, int op, int stage, const Pass
     }
   }
   if (on && r.a) hipEventRecord(r.a, s);
-  const int st = launch_pass(is_double, nt, parity, op, stage, a, grid, s);
-  if (on && r.b) {
+  const int st = launch();
+  if (on && r.a && r.b) {
     hipEventRecord(r.b, s);
-    int64_t tiles = int64_t(1) << (a.kq - nt);
-    const double amps = double(tiles) * double(1 << nt) * double(a.ncols);
-    r.kind = 3 * op + stage;
-    r.bytes = amps * slabs * (is_double ? 16.0 : 8.0);
-    r.flops = amps * double(a.ngates) * flops_per_amp_gate(op, stage, parity != 0);
+    r.kind = kind;
+    r.bytes = bytes;
+    r.flops = flops;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof.push_back(r);
   }
   return st;
+}
+
+int launch_prof(int is_double, int nt, int parity, int op, int stage, const PassArgs &a, int grid,
+                hipStream_t s, double slabs) {
+  const int64_t tiles = int64_t(1) << (a.kq - nt);
+  const double amps = double(tiles) * double(1 << nt) * double(a.ncols);
+  return prof_launch(s, 3 * op + stage, amps * slabs * (is_double ? 16.0 : 8.0),
+                     amps * double(a.ngates) * flops_per_amp_gate(op, stage, parity != 0),
+                     [&] { return launch_pass(is_double, nt, parity, op, stage, a, grid, s); });
 }
 
 int hip_check(hipError_t e, const char *what) {
@@ -907,6 +917,7 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
       a.ncols = ncols;
       a.ncg = ncg;
       a.n_items = (int)((int64_t(1) << (L.kq - 2)) * ncg);
+      const double slab_amps = double(H.rows) * double(ncols);  // amplitudes per state slab
       const int grid2 = (int)((std::min<int64_t>(a.n_items, kMaxWaves) + 3) / 4);
       // psi before every gate along pi (slab t = before the t-th gate of pi),
       // starting from |j> or from the input states
@@ -924,7 +935,8 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
         fill_pass(a, single[order[t - 1]], L);
         a.src_psi = slab(psi, t - 1);
         a.dst_psi = slab(psi, t);
-        if (launch_pass(L.is_double, 2, L.parity, OP_COST, ST_FWD, a, grid2, s))
+        if (prof_launch(s, 13, slab_amps * 2 * L.esize, slab_amps * (L.parity ? 16 : 32),
+                        [&] { return launch_pass(L.is_double, 2, L.parity, OP_COST, ST_FWD, a, grid2, s); }))
           return fail(RQ_EHIP, "forward state launch failed");
       }
       // phi at the output side of every gate along pi (slab = instance)
@@ -936,7 +948,8 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
         fill_pass(a, single[order[t]], L);
         a.src_psi = slab(phi, order[t]);
         a.dst_psi = slab(phi, order[t - 1]);
-        if (launch_pass(L.is_double, 2, L.parity, OP_COST, ST_FWD, a, grid2, s))
+        if (prof_launch(s, 13, slab_amps * 2 * L.esize, slab_amps * (L.parity ? 16 : 32),
+                        [&] { return launch_pass(L.is_double, 2, L.parity, OP_COST, ST_FWD, a, grid2, s); }))
           return fail(RQ_EHIP, "backward state launch failed");
       }
       // hole-array sweeps: hole at the t-th gate of pi, then the rest of its
@@ -951,8 +964,10 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
         const int h = order[t];
         if (!sweep[h]) continue;
         const int qh = c->pairs[2 * h], ql = c->pairs[2 * h + 1];
-        if (launch_hole(L.is_double, slab(psi, t), arr, H.rows, H.chunk, ncols, H.nd, c->n_qubits,
-                        qh, ql, L.parity, sector, s))
+        if (prof_launch(s, 14, slab_amps * (1 + H.nd) * L.esize, 0.0, [&] {
+              return launch_hole(L.is_double, slab(psi, t), arr, H.rows, H.chunk, ncols, H.nd,
+                                 c->n_qubits, qh, ql, L.parity, sector, s);
+            }))
           return fail(RQ_EHIP, "hole launch failed");
         if (launch_zero(slots, int64_t(rows_all) * kHessSlots, s))
           return fail(RQ_EHIP, "zero launch failed");
@@ -964,7 +979,9 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
           for (int b = 0; b < 8; ++b) ha.pos[b] = pp.pos[b];
           ha.ngates = (int)(pp.gates.size() - j0g);
           for (int g = 0; g < ha.ngates; ++g) ha.gates[g] = pp.gates[j0g + g];
-          if (launch_hess_pass(L.is_double, H.nt, L.parity, ha, gridh, s))
+          if (prof_launch(s, 12, slab_amps * (2 * H.nd + ha.ngates) * L.esize,
+                          slab_amps * H.nd * ha.ngates * (L.parity ? 32 : 64),
+                          [&] { return launch_hess_pass(L.is_double, H.nt, L.parity, ha, gridh, s); }))
             return fail(RQ_EHIP, "Hessian pass launch failed");
         }
         if (launch_accum_rows(slots, rows_all, kHessSlots, hh + size_t(h) * N * H.nd * H.ne, s))
@@ -1199,7 +1216,7 @@ int rq_profile_read(double *ms, int64_t *launches, double *bytes, double *flops)
     std::lock_guard<std::mutex> lk(g_prof_mu);
     recs.swap(g_prof);
   }
-  for (int i = 0; i < 12; ++i) {
+  for (int i = 0; i < kProfKinds; ++i) {
     if (ms) ms[i] = 0;
     if (launches) launches[i] = 0;
     if (bytes) bytes[i] = 0;
@@ -1210,7 +1227,7 @@ int rq_profile_read(double *ms, int64_t *launches, double *bytes, double *flops)
     float t = 0.f;
     if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
       st = fail(RQ_EHIP, "event timing failed");
-    if (r.kind >= 0 && r.kind < 12) {
+    if (r.kind >= 0 && r.kind < kProfKinds) {
       if (ms) ms[r.kind] += t;
       if (launches) launches[r.kind] += 1;
       if (bytes) bytes[r.kind] += r.bytes;

@@ -570,17 +570,19 @@ def rq_profile_enable(on: bool = True):
 def rq_profile_read():
     """Per (op, stage) kernel time (ms), launches, algorithmic bytes, flops
     since the last read (HIP events on the launch streams)."""
-    ms = np.zeros(12)
-    n = np.zeros(12, dtype=np.int64)
-    by = np.zeros(12)
-    fl = np.zeros(12)
+    ms = np.zeros(15)
+    n = np.zeros(15, dtype=np.int64)
+    by = np.zeros(15)
+    fl = np.zeros(15)
     _check(lib().rq_profile_read(_dptr(ms), n.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(by),
                                  _dptr(fl)), "rq_profile_read")
     out = {}
-    for i in range(12):
+    hess = {12: ("hess", "sweep"), 13: ("hess", "states"), 14: ("hess", "hole")}
+    for i in range(15):
         if n[i]:
-            out[(OPS[i // 3], STAGES[i % 3])] = dict(ms=float(ms[i]), launches=int(n[i]),
-                                                    bytes=float(by[i]), flops=float(fl[i]))
+            key = (OPS[i // 3], STAGES[i % 3]) if i < 12 else hess[i]
+            out[key] = dict(ms=float(ms[i]), launches=int(n[i]), bytes=float(by[i]),
+                            flops=float(fl[i]))
     return out
 
 
