@@ -294,6 +294,26 @@ def main():
             "roofline": roofline(hprof, hdom),
             "symmetric_rel": float(f"{np.abs(hr - hr.T).max() / np.abs(hr).max():.2e}")}
         log(f"[bench] Hessian: {dt:.2f} s")
+        # the same Hessian with particle-number-conserving gates (6 hole
+        # slices instead of 8)
+        c3n = rq.Circuit(prob.k, prob.pairs, param_of=prob.param_of, number=True, shift=4)
+        gn = w.number_haar_gates(np.random.default_rng([w.configs.SEED, 3, 300]), prob.n_params)
+        torch.cuda.synchronize()
+        rq.rq_profile_read()
+        rq.rq_profile_enable(True)
+        t0 = time.perf_counter()
+        rq.rq_hess_blocks(c3n, tgt64, gn, chunk=1024)
+        torch.cuda.synchronize()
+        dtn = time.perf_counter() - t0
+        rq.rq_profile_enable(False)
+        nprof = rq.rq_profile_read()
+        out["hessian_number_gates"] = {
+            "workload": "cfg3 circuit with particle-number-conserving gates (U(1) x U(2) x U(1), "
+                        "6 x 6 blocks, 6 hole slices), same target and symmetry",
+            "seconds": round(dtn, 3),
+            "sweep_ms": round(nprof[("hess", "sweep")]["ms"], 1),
+            "speedup_vs_parity_gates": round(dt / dtn, 3)}
+        log(f"[bench] Hessian (number gates): {dtn:.2f} s")
 
     if args.sampled_vectors > 0:
         # trace over random vectors instead of the 2^16 basis states (same

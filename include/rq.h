@@ -29,6 +29,13 @@
  *    in one parity sector p and are stored compressed: amplitude x (parity p)
  *    at row x >> 1 (the bit of qubit k-1 is implied).  A sector has 2^(k-1)
  *    basis columns j' = j >> 1.
+ *  - Particle-number mode (RQ_PARITY | RQ_NUMBER; the further restriction of
+ *    Sec. "Parity-conserving gate structure" that removes two parameters):
+ *    gates are U(1) x U(2) x U(1) on {00}, {01,10}, {11}, i.e. the parity
+ *    pattern without (0,3) and (3,0); those two entries are also ignored and
+ *    returned as zero.  States are stored as in parity mode; the Hessian
+ *    propagates 6 hole slices instead of 8 and its blocks have d = 6 entries
+ *    in the order (0,0),(3,3),(1,1),(1,2),(2,1),(2,2).
  *  - Precision: states and reference columns are stored and propagated in the
  *    target dtype; every contraction is accumulated in FP64 (per-lane partial
  *    sums of at most 2^(tile-2) products in the state precision, then FP64).
@@ -70,6 +77,7 @@ extern "C" {
 
 /* ---- circuit flags ------------------------------------------------------ */
 #define RQ_PARITY 1u      /* parity-conserving gates, sector-compressed states */
+#define RQ_NUMBER 2u      /* with RQ_PARITY: particle-number-conserving gates   */
 
 /* ---- operations (for rq_workspace_bytes) -------------------------------- */
 #define RQ_OP_COST  0
@@ -212,10 +220,12 @@ int rq_hvp(const rq_circuit *circuit, const rq_target *target,
  *   d_hess_holo  double[P][d][P][d][2]  holomorphic second derivatives
  *                d^2 h / dG_p[e] dG_q[e'] summed over instances, d = 16 entries
  *                (a,b) row-major, or d = 8 pattern entries in parity mode in
- *                the order (0,0),(0,3),(3,0),(3,3),(1,1),(1,2),(2,1),(2,2);
+ *                the order (0,0),(0,3),(3,0),(3,3),(1,1),(1,2),(2,1),(2,2),
+ *                or d = 6 in particle-number mode (the same order without
+ *                (0,3), (3,0));
  *   d_hess_real  double[P*d][P*d]   Riemannian Hessian in the orthonormal
  *                tangent basis X_{p,mu} = G_p A_mu documented in
- *                rq_tangent_basis (d = 16, or 8 in parity mode). */
+ *                rq_tangent_basis (d = 16, 8 in parity, 6 in number mode). */
 int rq_hess_blocks(const rq_circuit *circuit, const rq_target *target,
                    const double *gates, const rq_range *range,
                    const rq_exec *exec, double *d_f, double *d_egrad,
@@ -288,7 +298,10 @@ int rq_tr_accept(double f0, double f1, double model_decrease, double delta,
                  int32_t *accepted, double *rho);
 
 /* Orthonormal tangent basis A_mu (host output double[d][4][4][2]) used by
- * rq_hess_blocks / rq_tr_step: X_{p,mu} = G_p A_mu.  Returns d (16 or 8). */
+ * rq_hess_blocks / rq_tr_step: X_{p,mu} = G_p A_mu.  Returns d: 16 (U(4)),
+ * 8 with RQ_PARITY (U(2) x U(2)), 6 with RQ_PARITY | RQ_NUMBER
+ * (U(1) x U(2) x U(1): i E_00, i E_33, i E_11, i E_22, (E_12 - E_21)/sqrt2,
+ * i (E_12 + E_21)/sqrt2). */
 int rq_tangent_basis(uint32_t flags, double *basis);
 
 /* Diagnostics: gate instances per sweep pass chosen by the scheduler for op

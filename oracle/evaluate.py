@@ -18,7 +18,7 @@ from __future__ import annotations
 import numpy as np
 
 from .dense import cost, tangent_T
-from .riemann import PARITY_MASK, egrad, per_param, rgrad, rhvp
+from .riemann import egrad, gate_mask, per_param, rgrad, rhvp
 
 
 def evaluate(k, pairs, gates, param_of, direction, Ucols, cols=None, parity=False,
@@ -35,9 +35,10 @@ def evaluate(k, pairs, gates, param_of, direction, Ucols, cols=None, parity=Fals
     P = gates.shape[0]
     Tp = per_param(T, param_of, P)
     Tdp = per_param(Td, param_of, P)
-    if parity:
-        Tp = np.where(PARITY_MASK, Tp, 0)
-        Tdp = np.where(PARITY_MASK, Tdp, 0)
+    mask = gate_mask(parity)
+    if mask is not None:
+        Tp = np.where(mask, Tp, 0)
+        Tdp = np.where(mask, Tdp, 0)
     eg = egrad(Tp)
     out = dict(f=cost(k, pairs, inst, Ucols, cols, inputs), egrad=eg,
                rgrad=rgrad(gates, eg, parity))

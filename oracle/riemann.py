@@ -39,6 +39,28 @@ def _dag(A):
     return np.conj(np.swapaxes(A, -1, -2))
 
 
+# Particle-number-conserving gates (Sec. "Parity-conserving gate structure":
+# the further restriction that removes two more parameters): U(1) x U(2) x U(1)
+# on {00}, {01, 10}, {11}, i.e. the parity pattern without (0,3) and (3,0).
+NUMBER_MASK = np.array([[1, 0, 0, 0],
+                        [0, 1, 1, 0],
+                        [0, 1, 1, 0],
+                        [0, 0, 0, 1]], dtype=bool)
+
+
+def gate_mask(parity):
+    """Entry pattern of the gate manifold: None (U(4)), the parity pattern
+    (parity True / "parity") or the particle-number pattern ("number")."""
+    if parity == "number":
+        return NUMBER_MASK
+    return PARITY_MASK if parity else None
+
+
+def _masked(A, parity):
+    m = gate_mask(parity)
+    return A if m is None else np.where(m, A, 0)
+
+
 def per_param(T_inst: np.ndarray, param_of, n_params: int) -> np.ndarray:
     """Sum instance derivatives into parameter derivatives."""
     out = np.zeros((n_params,) + T_inst.shape[1:], dtype=T_inst.dtype)
@@ -58,9 +80,8 @@ def proj(V: np.ndarray, Y: np.ndarray) -> np.ndarray:
     return V @ (0.5 * (A - _dag(A)))
 
 
-def rgrad(V: np.ndarray, eg: np.ndarray, parity: bool = False) -> np.ndarray:
-    g = proj(V, eg)
-    return np.where(PARITY_MASK, g, 0) if parity else g
+def rgrad(V: np.ndarray, eg: np.ndarray, parity=False) -> np.ndarray:
+    return _masked(proj(V, eg), parity)
 
 
 def rhvp(V: np.ndarray, eg: np.ndarray, ehvp: np.ndarray, X: np.ndarray,
@@ -68,8 +89,7 @@ def rhvp(V: np.ndarray, eg: np.ndarray, ehvp: np.ndarray, X: np.ndarray,
     """Hess f(V)[X] = P_V(D egrad[X] - X sym(V^dagger egrad))."""
     S = _dag(V) @ eg
     sym = 0.5 * (S + _dag(S))
-    h = proj(V, ehvp - X @ sym)
-    return np.where(PARITY_MASK, h, 0) if parity else h
+    return _masked(proj(V, ehvp - X @ sym), parity)
 
 
 def real_basis(parity: bool = False):
@@ -78,6 +98,9 @@ def real_basis(parity: bool = False):
     basis vectors are X_mu = V A_mu; <V A, V B> = Re Tr[A^dagger B]."""
     E = lambda a, b: np.eye(4, dtype=np.complex128)[:, [a]] @ np.eye(4)[[b], :]  # noqa: E731
     r2 = np.sqrt(0.5)
+    if parity == "number":
+        return [1j * E(0, 0), 1j * E(3, 3),
+                1j * E(1, 1), 1j * E(2, 2), r2 * (E(1, 2) - E(2, 1)), 1j * r2 * (E(1, 2) + E(2, 1))]
     if parity:
         return [1j * E(0, 0), 1j * E(3, 3), r2 * (E(0, 3) - E(3, 0)), 1j * r2 * (E(0, 3) + E(3, 0)),
                 1j * E(1, 1), 1j * E(2, 2), r2 * (E(1, 2) - E(2, 1)), 1j * r2 * (E(1, 2) + E(2, 1))]

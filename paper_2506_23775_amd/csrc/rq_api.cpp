@@ -38,7 +38,7 @@ int launch_copy_cols(int is_double, const void *src, int64_t ld_src, int64_t col
 int launch_onehot(int is_double, void *dst, int64_t rows, int64_t ld, int64_t col0, int ncols,
                   void *s);
 int launch_accum_rows(const double *slots, int rows, int nslots, double *acc, void *s);
-int launch_hess_post(int N, int P, int d, const double *hh, const int32_t *inst_off,
+int launch_hess_post(int N, int P, int structure, const double *hh, const int32_t *inst_off,
                      const int32_t *inst_list, const int32_t *ppos, const int32_t *map,
                      const double *gates64,
                      const double *egrad,
@@ -142,7 +142,8 @@ int translation_map(const rq_circuit *c, std::vector<int> &tau) {
 int check_circuit(const rq_circuit *c) {
   if (!c) return fail(RQ_EINVAL, "circuit is NULL");
   const bool parity = c->flags & RQ_PARITY;
-  if (c->flags & ~RQ_PARITY) return fail(RQ_EINVAL, "unknown circuit flag");
+  if (c->flags & ~(RQ_PARITY | RQ_NUMBER)) return fail(RQ_EINVAL, "unknown circuit flag");
+  if ((c->flags & RQ_NUMBER) && !parity) return fail(RQ_EINVAL, "RQ_NUMBER requires RQ_PARITY");
   const int kmin = parity ? 4 : 2;
   if (c->n_qubits < kmin || c->n_qubits > 30 + (parity ? 1 : 0))
     return fail(RQ_EINVAL, "n_qubits out of range");
@@ -171,7 +172,7 @@ int check_circuit(const rq_circuit *c) {
 
 
 struct Layout {
-  int op = 0, is_double = 0, parity = 0, kq = 0, nt = 0, ne = 0, nbuf = 0;
+  int op = 0, is_double = 0, parity = 0, number = 0, kq = 0, nt = 0, ne = 0, nbuf = 0;
   int64_t chunk = 0, rows = 0;
   size_t esize = 0;
   std::vector<PlanPass> plan;
@@ -190,6 +191,7 @@ int make_layout(const rq_circuit *c, int32_t op_pub, int32_t dtype, int64_t chun
   L.op = op;
   L.is_double = dtype == RQ_C128;
   L.parity = (c->flags & RQ_PARITY) != 0;
+  L.number = (c->flags & RQ_NUMBER) != 0;
   L.kq = L.parity ? c->n_qubits - 1 : c->n_qubits;
   L.nt = tile_nt(L.kq, L.is_double, op);
   L.ne = entries(op, L.parity);
@@ -240,11 +242,15 @@ int make_layout(const rq_circuit *c, int32_t op_pub, int32_t dtype, int64_t chun
 // ---------------------------------------------------------------------------
 // Gate preprocessing (host, FP64)
 // ---------------------------------------------------------------------------
-void load_gate(const double *src, int p, bool parity, cd *M) {
+// Gate p of a host [P][4][4][2] array, entries off the mode's pattern set to
+// zero (parity: {0,3}x{0,3} + {1,2}x{1,2}; particle number additionally
+// without (0,3) and (3,0)).
+void load_gate(const double *src, int p, bool parity, cd *M, bool number = false) {
   for (int e = 0; e < 16; ++e) M[e] = cd(src[(size_t(p) * 16 + e) * 2], src[(size_t(p) * 16 + e) * 2 + 1]);
   if (parity) {
     bool keep[16] = {false};
     for (int c = 0; c < 8; ++c) keep[kParityIdx[c]] = true;
+    if (number) keep[3] = keep[12] = false;
     for (int e = 0; e < 16; ++e)
       if (!keep[e]) M[e] = 0.0;
   }
@@ -341,11 +347,11 @@ int prepare_upload(const rq_circuit *c, const Layout &L, const double *gates, co
   g_stage.assign(L.upload_bytes, 0);
   std::vector<cd> G(size_t(P) * 16), Gi(size_t(P) * 16), Z(size_t(P) * 16), GiZ(size_t(P) * 16);
   for (int p = 0; p < P; ++p) {
-    load_gate(gates, p, parity, &G[size_t(p) * 16]);
+    load_gate(gates, p, parity, &G[size_t(p) * 16], L.number);
     if (!invert_gate(&G[size_t(p) * 16], parity, &Gi[size_t(p) * 16]))
       return fail(RQ_ESINGULAR, "gate parameter " + std::to_string(p) + " is not invertible");
     if (dir) {
-      load_gate(dir, p, parity, &Z[size_t(p) * 16]);
+      load_gate(dir, p, parity, &Z[size_t(p) * 16], L.number);
       matmul4(&Gi[size_t(p) * 16], &Z[size_t(p) * 16], &GiZ[size_t(p) * 16]);
     }
   }
@@ -651,7 +657,8 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
   const double *g64 = reinterpret_cast<const double *>(ws + L.off_g64);
   const double *d64 = reinterpret_cast<const double *>(ws + L.off_d64);
   const int32_t *pof = reinterpret_cast<const int32_t *>(ws + L.off_pof);
-  if (launch_post(L.op, L.parity, (ex->flags & RQ_EXEC_ACCUMULATE) ? 1 : 0, c->n_params, N, pof,
+  if (launch_post(L.op, L.parity ? (L.number ? 2 : 1) : 0, (ex->flags & RQ_EXEC_ACCUMULATE) ? 1 : 0,
+                  c->n_params, N, pof,
                   tsum, L.ne, fsum, kMaxWaves, g64, d64, d_f, d_egrad, d_rgrad, d_ehvp, d_rhvp, s))
     return fail(RQ_EHIP, "post-processing launch failed");
   return RQ_OK;
@@ -677,7 +684,7 @@ int make_hess_layout(const rq_circuit *c, int32_t dtype, int64_t chunk, HessLayo
   const Layout &L = H.g;
   H.N = c->n_gates;
   H.P = c->n_params;
-  H.nd = L.parity ? 8 : 16;
+  H.nd = L.number ? 6 : L.parity ? 8 : 16;
   H.ne = L.parity ? 16 : 32;
   H.nt = L.kq >= 4 ? 4 : 2;
   H.esize = L.esize;
@@ -851,7 +858,7 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
               size_t(P) * 32 * sizeof(double));
   for (int l = 0; l < N; ++l) {  // transposed blocks, for phi <- G^T phi
     cd G[16], Gt[16];
-    load_gate(gates, param_of(c, l), L.parity, G);
+    load_gate(gates, param_of(c, l), L.parity, G, L.number);
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j) Gt[4 * i + j] = G[4 * j + i];
     char *d = hs.data() + (H.off_coefT - L.total) + size_t(l) * kCoefStride * L.esize;
@@ -860,7 +867,7 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
     else
       put_block<float>(d, Gt, L.parity);
   }
-  rq_tangent_basis(L.parity ? RQ_PARITY : 0u,
+  rq_tangent_basis(c->flags & (RQ_PARITY | RQ_NUMBER),
                    reinterpret_cast<double *>(hs.data() + (H.off_basis - L.total)));
   {
     int32_t *ioff = reinterpret_cast<int32_t *>(hs.data() + (H.off_ioff - L.total));
@@ -957,7 +964,11 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
       ha.ncols = ncols;
       ha.ncg = ncg;
       ha.n_items = (int)((int64_t(1) << (L.kq - H.nt)) * ncg * H.nd);
-      const int waves = (int)std::min<int64_t>(ha.n_items, kHessSlots);
+      // a wavefront keeps one slice (mu = wave % nd) over all its items, so
+      // when it takes several items the wavefront count is a multiple of nd
+      // (and of the 4 wavefronts of a block)
+      const int unit = H.nd % 4 == 0 ? H.nd : 4 * H.nd / (H.nd % 2 == 0 ? 2 : 1);
+      const int waves = ha.n_items <= kHessSlots ? ha.n_items : kHessSlots / unit * unit;
       const int gridh = (waves + 3) / 4;
       const int rows_all = N * H.nd * H.ne;
       for (int t = 0; t + 1 < N; ++t) {
@@ -966,7 +977,8 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
         const int qh = c->pairs[2 * h], ql = c->pairs[2 * h + 1];
         if (prof_launch(s, 14, slab_amps * (1 + H.nd) * L.esize, 0.0, [&] {
               return launch_hole(L.is_double, slab(psi, t), arr, H.rows, H.chunk, ncols, H.nd,
-                                 c->n_qubits, qh, ql, L.parity, sector, s);
+                                 c->n_qubits, qh, ql, L.parity ? (L.number ? 2 : 1) : 0,
+                                 sector, s);
             }))
           return fail(RQ_EHIP, "hole launch failed");
         if (launch_zero(slots, int64_t(rows_all) * kHessSlots, s))
@@ -993,7 +1005,8 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
   const int32_t *il = reinterpret_cast<const int32_t *>(ws + H.off_ilist);
   const int32_t *ppd = reinterpret_cast<const int32_t *>(ws + H.off_ppos);
   const int32_t *mapd = reinterpret_cast<const int32_t *>(ws + H.off_map);
-  if (launch_hess_post(N, P, H.nd, hh, ioff, il, ppd, mapd, reinterpret_cast<const double *>(ws + H.off_g64),
+  if (launch_hess_post(N, P, L.parity ? (L.number ? 2 : 1) : 0, hh, ioff, il, ppd, mapd,
+                       reinterpret_cast<const double *>(ws + H.off_g64),
                        eg_int, reinterpret_cast<const double *>(ws + H.off_basis), d_hh, d_hr, s))
     return fail(RQ_EHIP, "Hessian assembly launch failed");
   if (d_f) st = hip_check(hipMemcpyAsync(d_f, f_int, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
@@ -1038,7 +1051,7 @@ int rq_tr_solve(const rq_circuit *c, const rq_target *t, double *gates, const rq
   if (ex->workspace_bytes < need)
     return fail(RQ_ESPACE, "workspace too small: need " + std::to_string(need) + " bytes");
   const int P = H.P, d = H.nd, n = P * d;
-  const uint32_t flags = H.g.parity ? RQ_PARITY : 0u;
+  const uint32_t flags = c->flags & (RQ_PARITY | RQ_NUMBER);
   char *ws = static_cast<char *>(ex->workspace);
   const size_t off_f = align256(H.total), off_eg = align256(off_f + 256),
                off_hr = align256(off_eg + size_t(P) * 32 * sizeof(double));

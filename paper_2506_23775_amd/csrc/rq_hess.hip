@@ -160,7 +160,11 @@ __global__ void k_hole(const cx<R> *__restrict__ src, cx<R> *__restrict__ dst, i
     const int64_t x = (i / ld) % rows;
     const int mu = int(i / (ld * rows));
     int a, b;
-    if (parity) {
+    if (parity == 2) {  // particle number: (0,0),(3,3),(1,1),(1,2),(2,1),(2,2)
+      const int pa[6] = {0, 3, 1, 1, 2, 2}, pb[6] = {0, 3, 1, 2, 1, 2};
+      a = pa[mu];
+      b = pb[mu];
+    } else if (parity) {
       const int pa[8] = {0, 0, 3, 3, 1, 1, 2, 2}, pb[8] = {0, 3, 0, 3, 1, 2, 1, 2};
       a = pa[mu];
       b = pb[mu];
@@ -253,7 +257,7 @@ struct zc {
 __device__ inline zc zmul(zc a, zc b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
 __global__ __launch_bounds__(256) void k_hess_post(
-    int N, int P, int d, const double *__restrict__ hh, const int32_t *__restrict__ inst_off,
+    int N, int P, int structure, const double *__restrict__ hh, const int32_t *__restrict__ inst_off,
     const int32_t *__restrict__ inst_list, const int32_t *__restrict__ ppos,
     const int32_t *__restrict__ map, const double *__restrict__ gates64,
     const double *__restrict__ egrad, const double *__restrict__ basis, double *hess_holo,
@@ -262,16 +266,22 @@ __global__ __launch_bounds__(256) void k_hess_post(
   __shared__ zc Hh[256], Xp[256], Xq[256];
   __shared__ zc Sp[16];
   const int t = threadIdx.x;
-  // entry index e -> row-major 4x4 position
+  // structure 0: U(4), d = 16 entries row-major; 1: parity, d = 8 pattern
+  // entries; 2: particle number, d = 6 (the parity order without (0,3),
+  // (3,0)).  Stored blocks are [d hole slices][nec contraction entries].
+  const int d = structure == 0 ? 16 : structure == 1 ? 8 : 6;
+  const int nec = structure == 0 ? 16 : 8;
   const int pidx[8] = {0, 3, 12, 15, 5, 6, 9, 10};
-  auto epos = [&](int e) { return d == 8 ? pidx[e] : e; };
+  const int nsel[6] = {0, 3, 4, 5, 6, 7};
+  auto cidx = [&](int e) { return structure == 2 ? nsel[e] : e; };   // contraction entry
+  auto epos = [&](int e) { return structure == 0 ? e : pidx[cidx(e)]; };  // 4x4 position
   // entry (r, c) of the block of instance pair (l, m), l before m along the
   // sweep order: a stored block, or the transpose of one (translation classes)
   auto blk = [&](int l, int m, int r, int c) -> const double * {
     const int32_t v = map[int64_t(l) * N + m];
-    if (v >= 0) return hh + ((int64_t(v) * d + r) * 2 * d + 2 * c);
+    if (v >= 0) return hh + ((int64_t(v) * d + r) * nec + cidx(c)) * 2;
     const int64_t w = -int64_t(v) - 1;
-    return hh + ((w * d + c) * 2 * d + 2 * r);
+    return hh + ((w * d + c) * nec + cidx(r)) * 2;
   };
   if (t < d * d) {
     const int e = t / d, f = t % d;
@@ -444,12 +454,12 @@ int launch_accum_rows(const double *slots, int rows, int nslots, double *acc, vo
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_hess_post(int N, int P, int d, const double *hh, const int32_t *inst_off,
+int launch_hess_post(int N, int P, int structure, const double *hh, const int32_t *inst_off,
                      const int32_t *inst_list, const int32_t *ppos, const int32_t *map,
                      const double *gates64,
                      const double *egrad, const double *basis, double *hess_holo,
                      double *hess_real, void *s) {
-  hipLaunchKernelGGL(k_hess_post, dim3(P * P), dim3(256), 0, (hipStream_t)s, N, P, d, hh,
+  hipLaunchKernelGGL(k_hess_post, dim3(P * P), dim3(256), 0, (hipStream_t)s, N, P, structure, hh,
                      inst_off, inst_list, ppos, map, gates64, egrad, basis, hess_holo,
                      hess_real);
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -123,12 +123,15 @@ __device__ inline void unpack_T(const double *t, int parity, c64d *M) {
   }
 }
 
+// parity: 0 U(4), 1 parity pattern, 2 particle-number pattern (the parity
+// pattern without (0,3) and (3,0)).
 __device__ inline void store4(double *dst, const c64d *M, int parity, int accumulate) {
   for (int e = 0; e < 16; ++e) {
     bool keep = true;
     if (parity) {
       keep = false;
       for (int c = 0; c < 8; ++c) keep |= (kParityIdx[c] == e);
+      if (parity == 2 && (e == 3 || e == 12)) keep = false;
     }
     const double re = keep ? M[e].x : 0.0, im = keep ? M[e].y : 0.0;
     dst[2 * e] = accumulate ? dst[2 * e] + re : re;

@@ -22,8 +22,10 @@ namespace {
 // i E_aa (a = 0..3), (E_ab - E_ba)/sqrt2 and i (E_ab + E_ba)/sqrt2 for
 // (a,b) in 01,02,03,12,13,23.  Parity mode: i E_00, i E_33,
 // (E_03 - E_30)/sqrt2, i (E_03 + E_30)/sqrt2, i E_11, i E_22,
-// (E_12 - E_21)/sqrt2, i (E_12 + E_21)/sqrt2.
-int basis(bool parity, std::vector<cd> &B) {
+// (E_12 - E_21)/sqrt2, i (E_12 + E_21)/sqrt2.  Particle-number mode: the
+// parity basis without the two (0,3) elements.
+int basis(uint32_t flags, std::vector<cd> &B) {
+  const bool parity = (flags & RQ_PARITY) != 0, number = (flags & RQ_NUMBER) != 0;
   const double r = std::sqrt(0.5);
   const cd I(0, 1);
   auto E = [](std::vector<cd> &M, int a, int b, cd v) { M[4 * a + b] += v; };
@@ -36,10 +38,11 @@ int basis(bool parity, std::vector<cd> &B) {
       std::vector<cd> M(16);
       E(M, a, a, I); add(M);
       M.assign(16, 0.0); E(M, b, b, I); add(M);
+      if (number && k == 0) continue;
       M.assign(16, 0.0); E(M, a, b, r); E(M, b, a, -r); add(M);
       M.assign(16, 0.0); E(M, a, b, I * r); E(M, b, a, I * r); add(M);
     }
-    return 8;
+    return number ? 6 : 8;
   }
   for (int a = 0; a < 4; ++a) {
     std::vector<cd> M(16);
@@ -121,7 +124,7 @@ extern "C" {
 
 int rq_tangent_basis(uint32_t flags, double *out) {
   std::vector<cd> B;
-  const int d = basis((flags & RQ_PARITY) != 0, B);
+  const int d = basis(flags, B);
   if (out)
     for (int i = 0; i < d * 16; ++i) {
       out[2 * i] = B[i].real();
@@ -135,8 +138,7 @@ int rq_tr_step(int32_t n_params, uint32_t flags, const double *gates, const doub
                double *model_decrease, int32_t *stop) {
   if (n_params < 1 || !gates || !g || !H || !eta || !cand || !(delta > 0)) return RQ_EINVAL;
   std::vector<cd> B;
-  const bool parity = (flags & RQ_PARITY) != 0;
-  const int d = basis(parity, B);
+  const int d = basis(flags, B);
   const int n = n_params * d;
   auto dot = [n](const double *a, const double *b) {
     double s = 0;
@@ -225,7 +227,7 @@ int rq_tangent_coords(int32_t n_params, uint32_t flags, const double *gates, con
                       double *out) {
   if (n_params < 1 || !gates || !Y || !out) return RQ_EINVAL;
   std::vector<cd> B;
-  const int d = basis((flags & RQ_PARITY) != 0, B);
+  const int d = basis(flags, B);
   for (int p = 0; p < n_params; ++p) {
     cd G[16], Yp[16];
     for (int i = 0; i < 16; ++i) {

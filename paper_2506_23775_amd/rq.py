@@ -27,6 +27,7 @@ LIB_PATH = os.path.join(_HERE, "librq.so")
 RQ_OK, RQ_EINVAL, RQ_EHIP, RQ_ESPACE, RQ_ESINGULAR = 0, 1, 2, 3, 4
 RQ_C128, RQ_C64 = 0, 1
 RQ_PARITY = 1
+RQ_NUMBER = 2
 RQ_OP_COST, RQ_OP_GRAD, RQ_OP_HVP, RQ_OP_HESS, RQ_OP_APPLY = 0, 1, 2, 3, 4
 
 
@@ -143,7 +144,7 @@ class Circuit:
     """Gate topology: k qubits, pairs [(q_hi, q_lo)], optional param_of."""
 
     def __init__(self, k: int, pairs: Sequence, param_of=None, n_params: Optional[int] = None,
-                 parity: bool = False, shift: int = 0):
+                 parity: bool = False, shift: int = 0, number: bool = False):
         self.k = int(k)
         self.pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
         self.n_gates = self.pairs.shape[0]
@@ -153,9 +154,11 @@ class Circuit:
         else:
             self.param_of = np.ascontiguousarray(np.asarray(param_of, dtype=np.int32))
             self.n_params = int(self.param_of.max()) + 1 if n_params is None else int(n_params)
-        self.parity = bool(parity)
+        self.parity = bool(parity) or bool(number)
+        self.number = bool(number)      # particle-number-conserving gates (implies parity)
         self.shift = int(shift)   # translation symmetry (qubits), 0: none
-        self._c = _Circuit(self.k, self.n_gates, self.n_params, RQ_PARITY if parity else 0,
+        self.flags = (RQ_PARITY if self.parity else 0) | (RQ_NUMBER if self.number else 0)
+        self._c = _Circuit(self.k, self.n_gates, self.n_params, self.flags,
                            self.pairs.ctypes.data_as(C.POINTER(C.c_int32)),
                            None if self.param_of is None
                            else self.param_of.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -392,7 +395,7 @@ def rq_hess_blocks(circuit: Circuit, target: Target, gates, range=None, chunk=No
     g = _gates_host(gates)
     ex, ws = _exec(circuit, RQ_OP_HESS, target.dtype, chunk, workspace, stream)
     P = circuit.n_params
-    d = 8 if circuit.parity else 16
+    d = 6 if circuit.number else 8 if circuit.parity else 16
     f, eg, rg = _out((1,)), _out((P, 4, 4, 2)), _out((P, 4, 4, 2))
     hh = _out((P, d, P, d, 2), holomorphic)
     hr = _out((P * d, P * d))
@@ -424,15 +427,22 @@ def rq_apply_circuit(circuit: Circuit, gates, states: torch.Tensor, dtype: Optio
     return states
 
 
-def rq_tangent_basis(parity: bool = False) -> np.ndarray:
-    d = 8 if parity else 16
+def _structure_flags(parity):
+    """Circuit flags and tangent dimension for parity False / True / "number"."""
+    if parity == "number":
+        return RQ_PARITY | RQ_NUMBER, 6
+    return (RQ_PARITY, 8) if parity else (0, 16)
+
+
+def rq_tangent_basis(parity=False) -> np.ndarray:
+    flags, d = _structure_flags(parity)
     out = np.zeros((d, 4, 4), dtype=np.complex128)
-    n = lib().rq_tangent_basis(RQ_PARITY if parity else 0, _dptr(out))
+    n = lib().rq_tangent_basis(flags, _dptr(out))
     assert n == d
     return out
 
 
-def rq_tr_step(gates, g: np.ndarray, H: np.ndarray, delta: float, parity: bool = False):
+def rq_tr_step(gates, g: np.ndarray, H: np.ndarray, delta: float, parity=False):
     """Host FP64 truncated-CG step and polar retraction; returns
     (eta, candidate gates [P,4,4], model_decrease, stop_code)."""
     G = _gates_host(gates)
@@ -443,7 +453,7 @@ def rq_tr_step(gates, g: np.ndarray, H: np.ndarray, delta: float, parity: bool =
     cand = np.zeros_like(G)
     md = C.c_double(0)
     stop = C.c_int32(0)
-    _check(lib().rq_tr_step(P, RQ_PARITY if parity else 0, _dptr(G), _dptr(g), _dptr(H),
+    _check(lib().rq_tr_step(P, _structure_flags(parity)[0], _dptr(G), _dptr(g), _dptr(H),
                             float(delta), _dptr(eta), _dptr(cand), C.byref(md), C.byref(stop)),
            "rq_tr_step")
     return eta, cand, md.value, stop.value
@@ -458,13 +468,13 @@ def rq_tr_accept(f0, f1, model_decrease, delta, delta_bar, eta_norm):
     return nd.value, bool(acc.value), rho.value
 
 
-def rq_tangent_coords(gates, Y, parity: bool = False) -> np.ndarray:
+def rq_tangent_coords(gates, Y, parity=False) -> np.ndarray:
     """Coordinates Re Tr[(G_p A_mu)^dagger Y_p] in the tangent basis (host)."""
     G = _gates_host(gates)
     Yh = _gates_host(Y)
-    d = 8 if parity else 16
+    flags, d = _structure_flags(parity)
     out = np.zeros(G.shape[0] * d)
-    _check(lib().rq_tangent_coords(G.shape[0], RQ_PARITY if parity else 0, _dptr(G), _dptr(Yh),
+    _check(lib().rq_tangent_coords(G.shape[0], flags, _dptr(G), _dptr(Yh),
                                    _dptr(out)), "rq_tangent_coords")
     return out
 

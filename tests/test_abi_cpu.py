@@ -197,3 +197,34 @@ def test_tr_solve_rejects_bad_arguments(rq):
                        None, C.byref(n))
     assert st == rq.RQ_ESPACE          # 1 MiB is below rq_tr_workspace_bytes
     assert L.rq_tr_workspace_bytes(C.byref(circ._c), rq.RQ_C128, 64) > (1 << 20)
+
+
+def test_number_mode_host_functions(rq):
+    """Particle-number mode on the host: tangent basis, coordinates and one
+    trust-region step against the oracle; RQ_NUMBER needs RQ_PARITY."""
+    B = rq.rq_tangent_basis("number")
+    ref = np.stack(O.real_basis("number"))
+    assert np.abs(B - ref).max() < 1e-15
+    rng = np.random.default_rng(62)
+    P = 4
+    G = w.number_haar_gates(rng, P)
+    Y = np.where(w.NUMBER_MASK, rng.standard_normal((P, 4, 4)) + 1j * rng.standard_normal((P, 4, 4)), 0)
+    assert np.abs(rq.rq_tangent_coords(G, Y, "number") - O.gradient_real(G, Y, "number")).max() < 1e-13
+    n = 6 * P
+    A = rng.standard_normal((n, n))
+    H = A @ A.T / n + 0.1 * np.eye(n)
+    g = rng.standard_normal(n)
+    delta = 0.7
+    eta, cand, md, stop = rq.rq_tr_step(G, g, H, delta, "number")
+    ref = O.tr_step(G, 0.0, g, H, delta, lambda X: 0.0, parity="number")
+    assert np.abs(eta - ref["eta"]).max() < 1e-10
+    assert np.abs(cand - ref["candidate"]).max() < 1e-10
+    assert np.all(np.abs(cand[:, ~w.NUMBER_MASK]) < 1e-14)
+    L = rq.lib()
+    k = 6
+    pairs, _ = w.brickwall_pairs(k, 2)
+    bad = rq._Circuit(k, len(pairs), len(pairs), rq.RQ_NUMBER,
+                      np.ascontiguousarray(np.asarray(pairs, dtype=np.int32)).ctypes.data_as(
+                          C.POINTER(C.c_int32)), None, 0, 0)
+    assert L.rq_workspace_bytes(C.byref(bad), rq.RQ_OP_GRAD, rq.RQ_C128, 64) == 0
+    assert b"RQ_NUMBER" in L.rq_last_error()

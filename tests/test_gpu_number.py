@@ -1,0 +1,113 @@
+"""GPU parity of particle-number-conserving gates (U(1) x U(2) x U(1), the
+further restriction of Sec. "Parity-conserving gate structure"): f, both
+gradients and the HVP, the 6-entry Hessian blocks and the real Riemannian
+Hessian against the oracle, the translation-reduced Hessian, and the
+trust-region driver against the oracle's loop."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as w
+from gpu_helpers import oracle_eval, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: dict(f=1e-12, v=1e-10), 1: dict(f=1e-5, v=2e-5)}
+NSEL = [0, 15, 5, 6, 9, 10]   # row-major positions of (0,0),(3,3),(1,1),(1,2),(2,1),(2,2)
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import torch
+    from paper_2506_23775_amd import rq as _rq
+    assert torch.cuda.is_available()
+    _rq.lib()
+    return _rq
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _problem(rng, k, layers, shared):
+    pairs, layer = w.brickwall_pairs(k, layers)
+    param_of = np.asarray(layer if shared else np.arange(len(pairs)), dtype=np.int32)
+    P = int(param_of.max()) + 1
+    gates = w.number_haar_gates(rng, P)
+    direction = w.tangent_direction(rng, gates, parity="number")
+    return pairs, param_of, gates, direction
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("shared", [False, True])
+def test_number_sweeps_vs_oracle(rq, dtype, shared):
+    rng = np.random.default_rng([121, dtype, shared])
+    k = 8
+    pairs, param_of, gates, direction = _problem(rng, k, 4, shared)
+    U = w.target_unitary(4, 0.5, 1.0, 4.0)
+    circ = rq.Circuit(k, pairs, param_of=param_of, number=True)
+    tgt = rq.Target.from_dense(U, dtype, parity=True)
+    ref = oracle_eval(k, pairs, gates, param_of, direction, U, None, parity="number")
+    res = rq.rq_hvp(circ, tgt, gates, direction)
+    f = float(res[0])
+    assert abs(f - ref["f"]) <= TOL[dtype]["f"] * max(1.0, abs(ref["f"]))
+    for key, r in zip(["egrad", "rgrad", "ehvp", "rhvp"], res[1:]):
+        r = _np(r)
+        assert rel(r, ref[key]) <= TOL[dtype]["v"], key
+        assert np.all(r[:, ~w.NUMBER_MASK] == 0), key
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_number_hessian_vs_oracle(rq, dtype):
+    rng = np.random.default_rng([122, dtype])
+    k = 6
+    pairs, param_of, gates, _ = _problem(rng, k, 3, True)
+    U = w.target_unitary(3, 0.5, 1.0, 4.0)
+    circ = rq.Circuit(k, pairs, param_of=param_of, number=True)
+    tgt = rq.Target.from_dense(U, dtype, parity=True)
+    _, eg, _, hh, hr = rq.rq_hess_blocks(circ, tgt, gates, chunk=64)
+    inst = gates[param_of]
+    Hi = O.hessian_holomorphic(k, pairs, inst, U, mask=O.riemann.NUMBER_MASK)
+    P, N = gates.shape[0], len(pairs)
+    Hp = np.zeros((P, 4, 4, P, 4, 4), dtype=complex)
+    for l in range(N):
+        for m in range(N):
+            Hp[param_of[l], :, :, param_of[m]] += Hi[l, :, :, m]
+    Hh = Hp.reshape(P, 16, P, 16)[:, NSEL][:, :, :, NSEL]
+    assert rel(_np(hh), Hh) <= TOL[dtype]["v"] * 10
+    T = np.where(O.riemann.NUMBER_MASK, O.per_param(O.euclidean_T(k, pairs, inst, U), param_of, P), 0)
+    egr = O.egrad(T)
+    assert rel(_np(eg), egr) <= TOL[dtype]["v"]
+    Hr = O.hessian_real(gates, egr, Hp, "number")
+    assert rel(_np(hr), Hr) <= TOL[dtype]["v"] * 10
+    # translation-unique hole pairs give the same blocks
+    circ_s = rq.Circuit(k, pairs, param_of=param_of, number=True, shift=2)
+    _, _, _, hh2, hr2 = rq.rq_hess_blocks(circ_s, tgt, gates, chunk=64)
+    tol = 1e-12 if dtype == 0 else 2e-6
+    assert rel(_np(hh2), _np(hh)) <= tol
+    assert rel(_np(hr2), _np(hr)) <= tol
+
+
+def test_number_trust_region_vs_oracle(rq):
+    rng = np.random.default_rng(123)
+    k = 6
+    pairs, param_of, gates, _ = _problem(rng, k, 3, False)
+    U = w.target_unitary(3, 0.5, 1.0, 4.0)
+    circ = rq.Circuit(k, pairs, number=True)
+    tgt = rq.Target.from_dense(U, rq.RQ_C128, parity=True)
+    G, hist = rq.rq_tr_solve(circ, tgt, gates, max_iter=4, chunk=64)
+
+    def fgh(X):
+        T = np.where(O.riemann.NUMBER_MASK, O.euclidean_T(k, pairs, X, U), 0)
+        eg = O.egrad(T)
+        Hh = O.hessian_holomorphic(k, pairs, X, U, mask=O.riemann.NUMBER_MASK)
+        return (O.cost(k, pairs, X, U), O.gradient_real(X, eg, "number"),
+                O.hessian_real(X, eg, Hh, "number"))
+
+    Gr, hr = O.tr_solve(gates, fgh, lambda X: O.cost(k, pairs, X, U), 4, parity="number")
+    for a, b in zip(hist, hr):
+        assert abs(a[0] - b[0]) <= 1e-10 * max(1.0, abs(b[0]))
+        assert bool(a[4]) == bool(b[4])
+    assert np.abs(G - Gr).max() <= 1e-8
+    assert np.all(np.abs(G[:, ~w.NUMBER_MASK]) < 1e-14)

@@ -22,6 +22,8 @@ from .circuits import (  # noqa: F401
     random_states,
     haar_gates,
     parity_haar_gates,
+    number_haar_gates,
+    NUMBER_MASK,
     tangent_direction,
     PARITY_MASK,
 )

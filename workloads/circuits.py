@@ -76,15 +76,37 @@ def parity_haar_gates(rng: np.random.Generator, n: int) -> np.ndarray:
     return out
 
 
+def number_haar_gates(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Particle-number-conserving gates U(1) x U(2) x U(1) on {00}, {01, 10},
+    {11}: a Haar U(2) block on the odd states, then two uniform phases."""
+    out = np.zeros((n, 4, 4), dtype=np.complex128)
+    od = [1, 2]
+    for p in range(n):
+        out[p][np.ix_(od, od)] = haar_unitary(rng, 2)
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=2)
+        out[p][0, 0] = np.exp(1j * ph[0])
+        out[p][3, 3] = np.exp(1j * ph[1])
+    return out
+
+
+NUMBER_MASK = np.array([[1, 0, 0, 0],
+                        [0, 1, 1, 0],
+                        [0, 1, 1, 0],
+                        [0, 0, 0, 1]], dtype=bool)
+
+
 def tangent_direction(rng: np.random.Generator, gates: np.ndarray,
-                      parity: bool = False) -> np.ndarray:
+                      parity=False) -> np.ndarray:
     """Seeded random tangent vector X_p = G_p A_p with A_p the anti-Hermitian
     part of a complex Gaussian matrix (restricted to the parity pattern in
-    parity mode), normalised so that sum_p ||X_p||_F^2 = 1."""
+    parity mode, to the particle-number pattern for parity="number"),
+    normalised so that sum_p ||X_p||_F^2 = 1."""
     out = np.empty_like(gates)
     for p in range(gates.shape[0]):
         z = _complex_gaussian(rng, (4, 4))
-        if parity:
+        if parity == "number":
+            z = np.where(NUMBER_MASK, z, 0)
+        elif parity:
             z = np.where(PARITY_MASK, z, 0)
         a = 0.5 * (z - z.conj().T)
         out[p] = gates[p] @ a
