@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sampled-vectors", type=int, default=256,
                     help="random vectors per parity sector in the sampled-trace leg (0: skip)")
+    ap.add_argument("--orbits", type=int, default=1,
+                    help="1: time the translation-orbit-reduced evaluation (0: skip)")
     ap.add_argument("--hessian", type=int, default=1,
                     help="1: time the configuration-3 Hessian blocks (0: skip)")
     ap.add_argument("--tr-iters", type=int, default=5,
@@ -314,6 +316,30 @@ def main():
             "sweep_ms": round(nprof[("hess", "sweep")]["ms"], 1),
             "speedup_vs_parity_gates": round(dt / dtn, 3)}
         log(f"[bench] Hessian (number gates): {dtn:.2f} s")
+
+    if args.orbits:
+        # extension beyond the paper: one basis state per translation orbit
+        # (two-site shift of the brick wall and the Strang target), weighted
+        # by the orbit size -- the same f, gradient and HVP as the full sum
+        log("[bench] orbit-reduced trace (shift 4)")
+        c3o = rq.Circuit(prob.k, prob.pairs, param_of=prob.param_of, parity=True, shift=4)
+        tgt_o = rq.orbit_target(c3o, tgt64)
+        Ro = tgt_o.ref.shape[-1]
+        ro = gpu_run(rq, torch, c3o, tgt_o, prob, args.steps, args.warmup, args.chunk,
+                     basis_range=(-1, 0, Ro))
+        err = {}
+        for n, a, b in zip(["f", "egrad", "rgrad", "ehvp", "rhvp"], ro["result"], r64["result"]):
+            nb = np.linalg.norm(b)
+            err[n] = float(f"{np.linalg.norm(a - b) / (nb if nb else 1.0):.3e}")
+        out["orbit_reduced"] = {
+            "workload": "cfg3 with one basis state per orbit of the two-site translation "
+                        f"({Ro} columns per sector instead of 32768, orbit sizes as weights), c64",
+            "evals_per_s": round(args.steps / ro["seconds"], 4),
+            "ms_per_step": round(ro["seconds"] / args.steps * 1e3, 3),
+            "speedup_vs_full_sum": round(r64["seconds"] / ro["seconds"], 3),
+            "rel_diff_vs_full_sum": err}
+        del tgt_o
+        log(f"[bench] orbit-reduced: {ro['seconds'] / args.steps * 1e3:.1f} ms/eval")
 
     if args.sampled_vectors > 0:
         # trace over random vectors instead of the 2^16 basis states (same

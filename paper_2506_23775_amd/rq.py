@@ -569,6 +569,68 @@ def sampled_target(k: int, n_samples: int, rng: np.random.Generator, *, dtype: i
     return Target(ref, dtype, parity, inputs=inputs)
 
 
+def translation_orbits(k: int, shift: int, parity: bool = False):
+    """Orbit representatives of the basis states under the cyclic qubit
+    translation q -> q + shift, with their orbit sizes.  Returns a list of
+    (compressed columns, weights) per sector (one entry without parity)."""
+    n = 1 << k
+    x = np.arange(n, dtype=np.int64)
+    rot = x.copy()
+    best = x.copy()
+    # rotating the k-bit index right by `shift` bits moves qubit q to
+    # q + shift (qubit q is bit k-1-q)
+    for _ in range(k):
+        rot = ((rot >> shift) | (rot << (k - shift))) & (n - 1)
+        best = np.minimum(best, rot)
+        if np.all(rot == x):
+            break
+    reps, counts = np.unique(best, return_counts=True)
+    if not parity:
+        return [(reps, counts)]
+    par = np.array([bin(int(v)).count("1") & 1 for v in reps])
+    return [(reps[par == p] >> 1, counts[par == p]) for p in (0, 1)]
+
+
+def orbit_target(circuit: Circuit, target: Target, device="cuda") -> Target:
+    """Input states and target columns that reduce the trace sum to one basis
+    state per translation orbit, weighted by the orbit size: summand r starts
+    from sqrt(w_r)|r> and its target column is sqrt(w_r) U|r>, so every
+    output (bilinear in the two) is sum_r w_r (summand of r), which equals
+    the sum over all basis states when the circuit and the target are
+    invariant under circuit.shift (per-parameter outputs sum instances that
+    the translation permutes).  An extension of Sec. "Exploiting
+    translational invariance" from hole pairs to the basis sum.  Use with
+    range (-1, 0, R) (R = width of the returned slabs; parity sectors are
+    padded with zero columns to a common width)."""
+    if not circuit.shift:
+        raise ValueError("the circuit declares no translation symmetry")
+    if target.col_offset != 0 or target.inputs is not None:
+        raise ValueError("orbit reduction needs the full target columns")
+    k = circuit.k
+    orbs = translation_orbits(k, circuit.shift, circuit.parity)
+    R = max(len(r) for r, _ in orbs)
+    td = target.ref.dtype
+    rows = target.ref.shape[-2]
+    if circuit.parity:
+        inputs = torch.zeros((2, rows, R), dtype=td, device=device)
+        ref = torch.zeros((2, rows, R), dtype=td, device=device)
+        for p, (reps, wts) in enumerate(orbs):
+            m = len(reps)
+            sw = torch.from_numpy(np.sqrt(wts.astype(np.float64))).to(device)
+            idx = torch.from_numpy(reps).to(device)
+            inputs[p, idx, torch.arange(m, device=device)] = sw.to(td)
+            ref[p, :, :m] = target.ref[p].index_select(1, idx) * sw.to(td)[None, :]
+    else:
+        reps, wts = orbs[0]
+        m = len(reps)
+        sw = torch.from_numpy(np.sqrt(wts.astype(np.float64))).to(device)
+        idx = torch.from_numpy(reps).to(device)
+        inputs = torch.zeros((rows, R), dtype=td, device=device)
+        inputs[idx, torch.arange(m, device=device)] = sw.to(td)
+        ref = target.ref.index_select(1, idx) * sw.to(td)[None, :]
+    return Target(ref.contiguous(), target.dtype, circuit.parity, inputs=inputs)
+
+
 STAGES = ("fwd", "last", "bwd")
 OPS = ("cost", "grad", "hvp", "apply")
 

@@ -98,3 +98,55 @@ def test_shift_ignored_for_subrange_and_inputs(rq):
     b = _hess(rq, k, pairs, layer, gates, ti, True, 2, range=(-1, 0, 20), chunk=64)
     for x, y in zip(a, b):
         assert rel(y, x) <= 1e-13
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("case", ["parity_exact", "dense_exact", "parity_trotter"])
+def test_orbit_reduced_basis_sum_equals_full(rq, dtype, case):
+    """One basis state per translation orbit, weighted by the orbit size
+    (rq.orbit_target), reproduces the full basis sum of f, both gradients
+    and the HVP."""
+    rng = np.random.default_rng([104, dtype, len(case)])
+    k = 8
+    parity = case.startswith("parity")
+    layers = 5 if parity else 4
+    pairs, layer = w.brickwall_pairs(k, layers)
+    gates = (w.parity_haar_gates if parity else w.haar_gates)(rng, layers)
+    direction = w.tangent_direction(rng, gates, parity=parity)
+    if case.endswith("trotter"):
+        gl = w.strang_trotter_gates(4, 0.5, 4, 1.0, 4.0)
+        tgt = rq.build_trotter_target(k, gl, dtype=dtype, parity=True)
+        shift = 4
+    else:
+        tgt = rq.Target.from_dense(w.target_unitary(4, 0.5, 1.0, 4.0), dtype, parity=parity)
+        shift = 2
+    circ = rq.Circuit(k, pairs, param_of=layer, parity=parity, shift=shift)
+    full = [_np(x) for x in rq.rq_hvp(circ, tgt, gates, direction, chunk=64)]
+    ot = rq.orbit_target(circ, tgt)
+    R = ot.ref.shape[-1]
+    assert R < (1 << (k - 1 if parity else k)) * (3 if shift == 4 else 2) // 4
+    red = [_np(x) for x in rq.rq_hvp(circ, ot, gates, direction, range=(-1, 0, R), chunk=64)]
+    tol = 1e-12 if dtype == 0 else 2e-5
+    assert abs(red[0] - full[0]) <= tol * max(1.0, abs(full[0]))
+    for x, y in zip(red[1:], full[1:]):
+        assert rel(x, y) <= tol, rel(x, y)
+
+
+def test_orbit_reduced_config3(rq):
+    """Configuration 3 at k = 16 (Strang target, two-site symmetry): the
+    orbit-reduced evaluation (8264 + 8192 representatives instead of 2 x 2^15
+    basis states) agrees with the full one in c64 and c128."""
+    prob = w.make_problem(3, trotter_steps=20)
+    circ = rq.Circuit(prob.k, prob.pairs, param_of=prob.param_of, parity=True, shift=4)
+    for dtype, tol in ((rq.RQ_C128, 1e-11), (rq.RQ_C64, 2e-5)):
+        tgt = rq.build_trotter_target(prob.k, prob.trotter, dtype=dtype, parity=True)
+        full = [_np(x) for x in rq.rq_hvp(circ, tgt, prob.gates, prob.direction, chunk=2048)]
+        ot = rq.orbit_target(circ, tgt)
+        R = ot.ref.shape[-1]
+        assert R == 8264
+        red = [_np(x) for x in rq.rq_hvp(circ, ot, prob.gates, prob.direction, range=(-1, 0, R),
+                                          chunk=2048)]
+        assert abs(red[0] - full[0]) <= tol * max(1.0, abs(full[0]))
+        for x, y in zip(red[1:], full[1:]):
+            assert rel(x, y) <= tol, (dtype, rel(x, y))
+        del tgt, ot

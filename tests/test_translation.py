@@ -88,3 +88,53 @@ def test_declared_shift_is_checked(rq):
     assert L.rq_workspace_bytes(C.byref(odd._c), rq.RQ_OP_GRAD, rq.RQ_C128, 64) == 0
     rng_bad = rq.Circuit(k, pairs, param_of=layer, shift=k)
     assert L.rq_workspace_bytes(C.byref(rng_bad._c), rq.RQ_OP_GRAD, rq.RQ_C128, 64) == 0
+
+
+def _orbits_bruteforce(k, s):
+    """Orbit representatives and sizes of k-bit strings under the qubit
+    translation q -> q + s, by explicit bit lists."""
+    seen = {}
+    for x in range(1 << k):
+        bits = [(x >> (k - 1 - q)) & 1 for q in range(k)]
+        orb = set()
+        b = bits
+        for _ in range(k):
+            b = [b[(q - s) % k] for q in range(k)]
+            orb.add(sum(v << (k - 1 - q) for q, v in enumerate(b)))
+        seen[min(orb)] = len(orb)
+    reps = np.array(sorted(seen))
+    return reps, np.array([seen[r] for r in reps])
+
+
+@pytest.mark.parametrize("parity", [False, True])
+def test_orbit_weighted_representatives_equal_full_trace(parity):
+    """Extension beyond the paper: with a translation-invariant circuit and
+    target, the sum over one basis state per translation orbit, weighted by
+    the orbit size, equals the full basis sum for f, the per-parameter
+    gradients and the HVP (weights folded in as sqrt(w) on both sides)."""
+    rng = np.random.default_rng([92, parity])
+    k, layers = 6, 3
+    pairs, layer = w.brickwall_pairs(k, layers)
+    gates = (w.parity_haar_gates if parity else w.haar_gates)(rng, layers)
+    direction = w.tangent_direction(rng, gates, parity=parity)
+    U = w.target_unitary(k // 2, 0.5, 1.0, 4.0)
+    full = O.evaluate(k, pairs, gates, layer, direction, U, None, parity=parity)
+    reps, wts = _orbits_bruteforce(k, 2)
+    assert wts.sum() == 1 << k and len(reps) < (1 << k) // 2
+    Z = np.zeros((1 << k, len(reps)), dtype=complex)
+    Z[reps, np.arange(len(reps))] = np.sqrt(wts)
+    red = O.evaluate(k, pairs, gates, layer, direction, U @ Z, None, parity=parity, inputs=Z)
+    for key in full:
+        assert np.abs(np.asarray(red[key]) - np.asarray(full[key])).max() <= 1e-11, key
+
+
+def test_orbit_helper_matches_bruteforce(rq):
+    for k, s in ((8, 2), (8, 4), (6, 2)):
+        reps, wts = _orbits_bruteforce(k, s)
+        (r2, w2), = rq.translation_orbits(k, s)
+        assert np.array_equal(reps, r2) and np.array_equal(wts, w2)
+        sec = rq.translation_orbits(k, s, parity=True)
+        par = np.array([bin(int(v)).count("1") & 1 for v in reps])
+        for p in (0, 1):
+            assert np.array_equal(sec[p][0], reps[par == p] >> 1)
+            assert np.array_equal(sec[p][1], wts[par == p])
