@@ -444,6 +444,143 @@ __device__ __forceinline__ void bwd_gate(cx<R> (&ps)[NA], cx<R> (&dps)[NA], cx<R
   }
 }
 
+// bwd_gate with the forward states psi / dpsi held in LDS ([amplitude][lane],
+// this wavefront's tile) instead of registers: each 2x2 block (4-amplitude
+// group) reads its amplitudes, un-applies the gate and writes them back, so
+// only the backward states stay register resident.
+template <typename R, int NT, int MODE, bool HV, int C, int NE, int NA>
+__device__ __forceinline__ void bwd_gate_l(cx<R> *sps, cx<R> *sdps, int lane, cx<R> (&ph)[NA],
+                                           cx<R> (&dph)[NA], ccoef_t<R> *co, R (&tp)[NE]) {
+  auto ps = [&](int i) -> cx<R> & { return sps[i * 64 + lane]; };
+  auto dps = [&](int i) -> cx<R> & { return sdps[i * 64 + lane]; };
+  using K = Codes<MODE, NT>;
+  constexpr int TD = MODE == MODE_DENSE ? 32 : 16;  // offset of Tdot in tp
+  if constexpr (K::template valid<C>()) {
+    constexpr int H = K::template h<C>(), L = K::template l<C>();
+    if constexpr (MODE == MODE_DENSE) {
+      cx<R> g[16], gi[16], z[16], giz[16];
+      static_for<0, 16>([&](auto E) __attribute__((always_inline)) {
+        g[CV(E)] = ldco<R>(co, CV(E));
+        gi[CV(E)] = ldco<R>(co, 16 + CV(E));
+        if constexpr (HV) {
+          z[CV(E)] = ldco<R>(co, 32 + CV(E));
+          giz[CV(E)] = ldco<R>(co, 48 + CV(E));
+        }
+      });
+      for_groups<NT, H, L>([&](auto I0, auto I1, auto I2, auto I3) __attribute__((always_inline)) {
+        constexpr int id[4] = {CV(I0), CV(I1), CV(I2), CV(I3)};
+        cx<R> x[4], xd[4], p[4], pd[4];
+        static_for<0, 4>([&](auto A) __attribute__((always_inline)) {
+          constexpr int a = CV(A);
+          cx<R> y = mv2(gi[4 * a], ps(id[0]), gi[4 * a + 1], ps(id[1]));
+          cfma(y, gi[4 * a + 2], ps(id[2]));
+          cfma(y, gi[4 * a + 3], ps(id[3]));
+          x[a] = y;
+          p[a] = ph[id[a]];
+        });
+        if constexpr (HV) {
+          static_for<0, 4>([&](auto A) __attribute__((always_inline)) {
+            constexpr int a = CV(A);
+            cx<R> y = mv2(gi[4 * a], dps(id[0]), gi[4 * a + 1], dps(id[1]));
+            cfma(y, gi[4 * a + 2], dps(id[2]));
+            cfma(y, gi[4 * a + 3], dps(id[3]));
+            cx<R> m = mv2(giz[4 * a], x[0], giz[4 * a + 1], x[1]);
+            cfma(m, giz[4 * a + 2], x[2]);
+            cfma(m, giz[4 * a + 3], x[3]);
+            y.x -= m.x;
+            y.y -= m.y;
+            xd[a] = y;
+            pd[a] = dph[id[a]];
+          });
+        }
+        static_for<0, 16>([&](auto AB) __attribute__((always_inline)) {
+          constexpr int a = CV(AB) / 4, b = CV(AB) % 4, e = 2 * CV(AB);
+          cacc(tp[e], tp[e + 1], p[a], x[b]);
+          if constexpr (HV) {
+            cacc(tp[TD + e], tp[TD + e + 1], pd[a], x[b]);
+            cacc(tp[TD + e], tp[TD + e + 1], p[a], xd[b]);
+          }
+        });
+        static_for<0, 4>([&](auto A) __attribute__((always_inline)) {
+          constexpr int a = CV(A);
+          cx<R> y = mv2(g[a], p[0], g[4 + a], p[1]);
+          cfma(y, g[8 + a], p[2]);
+          cfma(y, g[12 + a], p[3]);
+          ph[id[a]] = y;
+          ps(id[a]) = x[a];
+          if constexpr (HV) {
+            cx<R> yd = mv2(g[a], pd[0], g[4 + a], pd[1]);
+            cfma(yd, g[8 + a], pd[2]);
+            cfma(yd, g[12 + a], pd[3]);
+            cfma(yd, z[a], p[0]);
+            cfma(yd, z[4 + a], p[1]);
+            cfma(yd, z[8 + a], p[2]);
+            cfma(yd, z[12 + a], p[3]);
+            dph[id[a]] = yd;
+            dps(id[a]) = xd[a];
+          }
+        });
+      });
+    } else {
+      constexpr int KD = K::template kind<C>(), PI = K::template pi<C>();
+      cx<R> g[8], gi[8], z[8], giz[8];
+      static_for<0, 8>([&](auto E) __attribute__((always_inline)) {
+        g[CV(E)] = ldco<R>(co, CV(E));
+        gi[CV(E)] = ldco<R>(co, 16 + CV(E));
+        if constexpr (HV) {
+          z[CV(E)] = ldco<R>(co, 32 + CV(E));
+          giz[CV(E)] = ldco<R>(co, 48 + CV(E));
+        }
+      });
+      for_blocks<NT, KD, H, L, PI>([&](auto J0, auto J1, auto C00, auto C01, auto C10,
+                                       auto C11) __attribute__((always_inline)) {
+        constexpr int i0 = CV(J0), i1 = CV(J1);
+        constexpr int c00 = CV(C00), c01 = CV(C01), c10 = CV(C10), c11 = CV(C11);
+        const cx<R> x0 = mv2(gi[c00], ps(i0), gi[c01], ps(i1));
+        const cx<R> x1 = mv2(gi[c10], ps(i0), gi[c11], ps(i1));
+        const cx<R> p0 = ph[i0], p1 = ph[i1];
+        cacc(tp[2 * c00], tp[2 * c00 + 1], p0, x0);
+        cacc(tp[2 * c01], tp[2 * c01 + 1], p0, x1);
+        cacc(tp[2 * c10], tp[2 * c10 + 1], p1, x0);
+        cacc(tp[2 * c11], tp[2 * c11 + 1], p1, x1);
+        if constexpr (HV) {
+          cx<R> xd0 = mv2(gi[c00], dps(i0), gi[c01], dps(i1));
+          cx<R> xd1 = mv2(gi[c10], dps(i0), gi[c11], dps(i1));
+          const cx<R> m0 = mv2(giz[c00], x0, giz[c01], x1);
+          const cx<R> m1 = mv2(giz[c10], x0, giz[c11], x1);
+          xd0.x -= m0.x;
+          xd0.y -= m0.y;
+          xd1.x -= m1.x;
+          xd1.y -= m1.y;
+          const cx<R> q0 = dph[i0], q1 = dph[i1];
+          cacc(tp[TD + 2 * c00], tp[TD + 2 * c00 + 1], q0, x0);
+          cacc(tp[TD + 2 * c01], tp[TD + 2 * c01 + 1], q0, x1);
+          cacc(tp[TD + 2 * c10], tp[TD + 2 * c10 + 1], q1, x0);
+          cacc(tp[TD + 2 * c11], tp[TD + 2 * c11 + 1], q1, x1);
+          cacc(tp[TD + 2 * c00], tp[TD + 2 * c00 + 1], p0, xd0);
+          cacc(tp[TD + 2 * c01], tp[TD + 2 * c01 + 1], p0, xd1);
+          cacc(tp[TD + 2 * c10], tp[TD + 2 * c10 + 1], p1, xd0);
+          cacc(tp[TD + 2 * c11], tp[TD + 2 * c11 + 1], p1, xd1);
+          cx<R> y0 = mv2(g[c00], q0, g[c10], q1);
+          cfma(y0, z[c00], p0);
+          cfma(y0, z[c10], p1);
+          cx<R> y1 = mv2(g[c01], q0, g[c11], q1);
+          cfma(y1, z[c01], p0);
+          cfma(y1, z[c11], p1);
+          dph[i0] = y0;
+          dph[i1] = y1;
+          dps(i0) = xd0;
+          dps(i1) = xd1;
+        }
+        ph[i0] = mv2(g[c00], p0, g[c10], p1);
+        ph[i1] = mv2(g[c01], p0, g[c11], p1);
+        ps(i0) = x0;
+        ps(i1) = x1;
+      });
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Wavefront reduce-scatter of V = 2^LV per-lane values (LV <= 6).  Step s
 // pairs every lane with a partner that differs in lane bit d_s = 5 - s; the
@@ -593,6 +730,16 @@ struct Prefetch {
                                              : (OP == OP_HVP ? 0xf : 0x3);
 };
 
+// Backward passes that keep the forward states (checkpoint psi, dpsi) in LDS
+// for the whole tile -- loaded there by direct global->LDS loads, un-applied
+// block by block in place -- so that only phi (+dphi) and the contraction
+// partials occupy registers and two wavefronts fit per SIMD.  Their LDS holds
+// exactly the checkpoint slabs of Prefetch (no look-ahead tile).
+template <typename R, int NT, int MODE, int OP>
+struct Resident {
+  static constexpr bool value = sizeof(R) == 4 && OP == OP_HVP && MODE == MODE_PARITY;
+};
+
 template <typename R, int NT, int MODE, int OP, int STAGE>
 struct Occupancy {
   static constexpr int words = sizeof(R) / 4;
@@ -603,9 +750,11 @@ struct Occupancy {
                                  : 0;
   static constexpr int regs = (1 << NT) * 2 * words * nst + acc + 80;
   static constexpr int w = 512 / (regs + regs / 4);
-  // Backward-type kernels keep the compiler's own allocation: at two waves per
-  // SIMD they would spill to scratch memory.
-  static constexpr int value = STAGE != ST_FWD ? 1 : (w < 1 ? 1 : (w > 8 ? 8 : w));
+  // Backward-type kernels keep the compiler's own allocation (at two waves per
+  // SIMD their register-resident states would spill to scratch memory),
+  // except those with LDS-resident forward states.
+  static constexpr int value = (STAGE == ST_BWD && Resident<R, NT, MODE, OP>::value) ? 2
+                               : STAGE != ST_FWD ? 1 : (w < 1 ? 1 : (w > 8 ? 8 : w));
 };
 
 template <typename R, int NT, int MODE, int OP, int STAGE>
@@ -627,6 +776,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((
   // psi, 1 phi, 2 checkpoint dpsi, 3 dphi); the others are loaded into
   // registers at the top of the tile.
   constexpr bool PF = STAGE == ST_BWD;
+  constexpr bool LRES = PF && Resident<R, NT, MODE, OP>::value;   // forward states in LDS
   constexpr int DW = int(ES) / 4;                 // dwords per amplitude
   constexpr int PFMASK = Prefetch<R, NT, OP>::mask;
   constexpr int NPF = __builtin_popcount(PFMASK);
@@ -745,9 +895,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((
       return ldrow<R>(reinterpret_cast<const char *>(base) + rowb + boff(I), voff);
     }
   };
-  if constexpr (PF) {
+  if constexpr (PF && !LRES) {
     if (gwave < A.n_items) prefetch(gwave);
   }
+  cx<R> *sps = reinterpret_cast<cx<R> *>(pf);          // LRES: psi tile [amp][lane]
+  cx<R> *sdps = sps + NA * 64;                          // LRES: dpsi tile
 
   for (int item = gwave; item < A.n_items; item += nwaves) {
     const int cg = item % A.ncg;
@@ -816,6 +968,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((
           }
         }
       }
+    } else if constexpr (LRES) {
+      // this tile's checkpoint slabs straight into LDS (after the previous
+      // tile's LDS accesses completed), phi (+dphi) into registers
+      wait_lgkm0();
+      prefetch(item);
+      static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+        const cx<R> p = pf_read(ic<1>{}, I, rowb, voff);
+        ph[CV(I)] = ok ? p : zero;
+        if constexpr (HV) {
+          const cx<R> pd = pf_read(ic<3>{}, I, rowb, voff);
+          dph[CV(I)] = ok ? pd : zero;
+        }
+      });
+      wait_vmcnt<0>();
+      if (!ok) {  // padding columns of a ragged chunk: zero states
+        static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+          sps[CV(I) * 64 + lane] = zero;
+          if constexpr (HV) sdps[CV(I) * 64 + lane] = zero;
+        });
+      }
     } else {
       // Wait for this tile's prefetch.  Only the previous tile's phi stores
       // (nst * NA vector-memory instructions) were issued after it, so they
@@ -870,7 +1042,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((
         R tp[NE];
         static_for<0, NE>([&](auto E) __attribute__((always_inline)) { tp[CV(E)] = R(0); });
         dispatch<0, K::n>(gate_code(MODE, NT, gr, pi), [&](auto CC) __attribute__((always_inline)) {
-          bwd_gate<R, NT, MODE, HV, CV(CC), NE>(ps, dps, ph, dph, co, tp);
+          if constexpr (LRES)
+            bwd_gate_l<R, NT, MODE, HV, CV(CC), NE>(sps, sdps, lane, ph, dph, co, tp);
+          else
+            bwd_gate<R, NT, MODE, HV, CV(CC), NE>(ps, dps, ph, dph, co, tp);
         });
         const double r = wave_reduce_scatter<R, NE>(tp, lane);
         if (writer) acc[g * NE + my_e] += r;
