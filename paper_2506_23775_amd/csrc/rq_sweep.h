@@ -724,10 +724,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 // 1 phi, 2 checkpoint dpsi, 3 dphi).  Complex64 prefetches only the
 // checkpoints: 16 KB of LDS per wavefront at 16 amplitudes leave room for two
 // wavefronts per SIMD.
-template <typename R, int NT, int OP>
+template <typename R, int NT, int MODE, int OP>
 struct Prefetch {
-  static constexpr int mask = sizeof(R) == 4 ? (OP == OP_HVP ? 0x5 : 0x1)
-                                             : (OP == OP_HVP ? 0xf : 0x3);
+  static constexpr int mask =
+      (sizeof(R) == 4 || (MODE == MODE_PARITY && OP == OP_GRAD)) ? (OP == OP_HVP ? 0x5 : 0x1)
+                                                                 : (OP == OP_HVP ? 0xf : 0x3);
 };
 
 // Backward passes that keep the forward states (checkpoint psi, dpsi) in LDS
@@ -737,7 +738,8 @@ struct Prefetch {
 // exactly the checkpoint slabs of Prefetch (no look-ahead tile).
 template <typename R, int NT, int MODE, int OP>
 struct Resident {
-  static constexpr bool value = sizeof(R) == 4 && OP == OP_HVP && MODE == MODE_PARITY;
+  static constexpr bool value =
+      MODE == MODE_PARITY && (OP == OP_GRAD || (OP == OP_HVP && sizeof(R) == 4));
 };
 
 template <typename R, int NT, int MODE, int OP, int STAGE>
@@ -778,7 +780,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((
   constexpr bool PF = STAGE == ST_BWD;
   constexpr bool LRES = PF && Resident<R, NT, MODE, OP>::value;   // forward states in LDS
   constexpr int DW = int(ES) / 4;                 // dwords per amplitude
-  constexpr int PFMASK = Prefetch<R, NT, OP>::mask;
+  constexpr int PFMASK = Prefetch<R, NT, MODE, OP>::mask;
   constexpr int NPF = __builtin_popcount(PFMASK);
   constexpr int PF_BYTES = PF ? NPF * NA * 64 * int(ES) : 0;
   const int lane = threadIdx.x & 63;
@@ -1093,7 +1095,7 @@ static int launch_one(const PassArgs &a, int grid, void *stream) {
   if constexpr (STAGE == ST_BWD) {
     // one wavefront per block: grid * 4 blocks of 64 threads give the same
     // wavefronts (and slot indices) as grid blocks of 256 threads
-    constexpr int NPF = __builtin_popcount(Prefetch<R, NT, OP>::mask);
+    constexpr int NPF = __builtin_popcount(Prefetch<R, NT, MODE, OP>::mask);
     const size_t lds = size_t(NPF) * (1 << NT) * 64 * sizeof(cx<R>) +
                        size_t(kMaxGates) * NE * sizeof(double);
     hipLaunchKernelGGL((k_pass<R, NT, MODE, OP, STAGE>), dim3(grid * (kBlock / 64)), dim3(64),
