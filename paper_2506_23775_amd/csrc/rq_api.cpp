@@ -43,9 +43,9 @@ int launch_hess_post(int N, int P, int structure, const double *hh, const int32_
                      const double *gates64,
                      const double *egrad,
                      const double *basis, double *hess_holo, double *hess_real, void *s);
-// FP64 partial-sum slots (one per wavefront) of the Hessian sweeps: 2048
-// wavefronts, two per SIMD.
-constexpr int kHessSlots = 2048;
+// FP64 partial-sum slots (one per wavefront) of the Hessian sweeps: 3072
+// wavefronts, three per SIMD (a multiple of 4 x 6, 8 and 16 slices).
+constexpr int kHessSlots = 3072;
 }  // namespace rqk
 
 namespace {
