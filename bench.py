@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sampled-vectors", type=int, default=256,
                     help="random vectors per parity sector in the sampled-trace leg (0: skip)")
+    ap.add_argument("--config4", type=int, default=2,
+                    help="timed evaluations of configuration 4 (dense gates; 0: skip)")
     ap.add_argument("--orbits", type=int, default=1,
                     help="1: time the translation-orbit-reduced evaluation (0: skip)")
     ap.add_argument("--hessian", type=int, default=1,
@@ -316,6 +318,30 @@ def main():
             "sweep_ms": round(nprof[("hess", "sweep")]["ms"], 1),
             "speedup_vs_parity_gates": round(dt / dtn, 3)}
         log(f"[bench] Hessian (number gates): {dtn:.2f} s")
+
+    if args.config4:
+        # configuration 4: k = 16 general mode, 9-layer brick wall of 72
+        # independent Haar U(4) gates, the same Strang target without parity
+        # compression (2^16 x 2^16 columns, c64)
+        log("[bench] configuration 4 (dense gates): building the general-mode target")
+        p4 = w.make_problem(4, trotter_steps=args.trotter_steps)
+        c4 = rq.Circuit(p4.k, p4.pairs, param_of=p4.param_of)
+        t4 = rq.build_trotter_target(p4.k, p4.trotter, dtype=rq.RQ_C64, parity=False)
+        r4 = gpu_run(rq, torch, c4, t4, p4, args.config4, 1, min(args.chunk, 2048))
+        dom4 = max(r4["prof"].items(), key=lambda kv: kv[1]["ms"])[0]
+        out["config4"] = {
+            "workload": "cfg4: k=16, 9-layer brick wall, 72 independent Haar U(4) gates, "
+                        "Strang-200 target, 2^16 basis states, c64 states + FP64 accumulation",
+            "evals_per_s": round(args.config4 / r4["seconds"], 4),
+            "ms_per_step": round(r4["seconds"] / args.config4 * 1e3, 2),
+            "kernels": {f"{k[0]}/{k[1]}": dict(ms=round(v["ms"], 1), launches=v["launches"],
+                                               GBps=round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1),
+                                               TFLOPs=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2))
+                        for k, v in r4["prof"].items()},
+            "roofline": roofline(r4["prof"], dom4)}
+        del t4
+        torch.cuda.empty_cache()
+        log(f"[bench] configuration 4: {out['config4']['ms_per_step']} ms/eval")
 
     if args.orbits:
         # extension beyond the paper: one basis state per translation orbit
