@@ -228,3 +228,12 @@ def test_number_mode_host_functions(rq):
                           C.POINTER(C.c_int32)), None, 0, 0)
     assert L.rq_workspace_bytes(C.byref(bad), rq.RQ_OP_GRAD, rq.RQ_C128, 64) == 0
     assert b"RQ_NUMBER" in L.rq_last_error()
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without librq.so the binding raises instead of falling back."""
+    from paper_2506_23775_amd import rq as _rq
+    monkeypatch.setattr(_rq, "_lib", None)
+    monkeypatch.setattr(_rq, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "librq.so"))
+    with pytest.raises(RuntimeError, match="no fallback"):
+        _rq.lib()

@@ -150,3 +150,40 @@ def test_deterministic_repeat(rq):
     b = rq.rq_hvp(circ, tgt, prob.gates, prob.direction)
     for x, y in zip(a, b):
         assert np.array_equal(_np(x), _np(y))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_large_state_k20_window(rq, dtype):
+    """2^20-row states (k = 20 general, k = 21 parity): at chunk 256 a
+    complex128 slab is 4 GiB, so row offsets pass 2^31 bytes; the last two
+    basis columns against the oracle on the same columns."""
+    import torch
+    rng = np.random.default_rng([11, dtype])
+    for k, parity in ((20, False), (21, True)):
+        pairs, layer = w.brickwall_pairs(k if k % 2 == 0 else k - 1, 1)
+        gates = (w.parity_haar_gates if parity else w.haar_gates)(rng, 1)
+        direction = w.tangent_direction(rng, gates, parity=parity)
+        n = 1 << (k - 1) if parity else 1 << k
+        width = 2
+        j0 = n - width
+        V = w.random_states(rng, n, width)
+        td = rq.torch_dtype(dtype)
+        if parity:
+            ref = torch.zeros((2, n, width), dtype=td, device="cuda")
+            ref[1] = torch.from_numpy(V).to(td).cuda()
+            full = np.zeros((1 << k, width), dtype=complex)
+            full[sector_full_index(k, 1, np.arange(n))] = V
+            cols = sector_full_index(k, 1, np.arange(j0, j0 + width))
+            rng_ = (1, j0, width)
+        else:
+            ref = torch.from_numpy(V).to(td).cuda()
+            full = V
+            cols = np.arange(j0, j0 + width)
+            rng_ = (-1, j0, width)
+        tgt = rq.Target(ref.contiguous(), dtype, parity, col_offset=j0)
+        circ = rq.Circuit(k, pairs, param_of=layer, parity=parity)
+        refv = oracle_eval(k, pairs, gates, layer, direction, full, cols, parity=parity)
+        _check(rq.rq_hvp(circ, tgt, gates, direction, range=rng_, chunk=256), refv, dtype,
+               f"k={k} parity={parity}")
+        del tgt, ref
+        torch.cuda.empty_cache()
