@@ -66,6 +66,28 @@ def gpu_run(rq, torch, circ, target, prob, steps, warmup, chunk, basis_range=Non
     return dict(seconds=t1 - t0, lat_ms=lat, prof=prof, result=res, ws_bytes=ws_need)
 
 
+def copy_bandwidth(torch, nbytes=4 << 30, reps=10):
+    """Read+write rate of a plain device copy (torch's copy kernel) of nbytes:
+    the practical HBM rate for streaming kernels on this GPU, reported next
+    to the 8 TB/s datasheet peak."""
+    x = torch.empty(nbytes // 8, dtype=torch.complex64, device="cuda")
+    x.real.fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / (ms / 1e3) / 1e9, 1)
+
+
 def _pcts(lat_ms):
     """Per-evaluation latency percentiles (HIP events around each step)."""
     return {f"p{q}": round(float(np.percentile(lat_ms, q)), 3) for q in (10, 50, 90, 99)}
@@ -272,6 +294,7 @@ def main():
     out["roofline"] = roofline(r64["prof"], dom)
     if args.chunk == 4096:
         out["roofline"]["traffic"] = measured_traffic(f"{dom[0]}/{dom[1]}")
+    out["roofline"]["copy_ref_GBps"] = copy_bandwidth(torch)
 
     if args.hessian:
         # all pairwise Hessian blocks of configuration 3 over the full trace,
