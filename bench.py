@@ -122,22 +122,33 @@ def roofline(prof, key):
                          frac=round(hbm_frac, 4)))
 
 
+def code_hash(path):
+    """sha256[:16] of a source file's code with comments and whitespace
+    removed, so that edits of comments keep a stored measurement valid."""
+    import hashlib
+    import re
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    txt = re.sub(r"//[^\n]*", "", txt)
+    txt = re.sub(r"\s+", "", txt)
+    return hashlib.sha256(txt.encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel_key):
     """HBM bytes per launch of a sweep kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on a copy
-    kernel), or None when the kernel source changed since it was taken."""
-    import hashlib
+    kernel), or None when the kernel code changed since it was taken."""
     prof = os.path.join(ROOT, "profiles", "k_pass_hvp_cfg3_c64.txt")
     src = os.path.join(ROOT, "paper_2506_23775_amd", "csrc", "rq_sweep.h")
     if not (os.path.exists(prof) and os.path.exists(src)):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = code_hash(src)
     vals = {}
     for line in open(prof):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_sha256_16") != sha:
+    if vals.get("code_sha256_16") != sha:
         return None
     v = vals.get(f"traffic_bytes_per_launch[{kernel_key}]")
     return float(v) if v else None

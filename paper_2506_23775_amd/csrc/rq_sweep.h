@@ -119,10 +119,10 @@ __device__ __forceinline__ void strow(char *row, uint32_t voff, cx<R> v) {
 }
 
 // Direct global->LDS loads (gfx950): each lane of the wavefront writes its
-// `size` bytes at lds + lane * size.  Used to prefetch the next tile of the
-// backward sweep while the current one is computed from registers.  The
-// compiler does not order these against later LDS reads, so the kernel waits
-// on vmcnt explicitly (see k_pass).
+// `size` bytes at lds + lane * size.  Used by the backward sweep to bring
+// checkpoint slabs into LDS (the current tile, kept there, or the next one,
+// prefetched).  The compiler does not order these against later LDS reads,
+// so the kernel waits on vmcnt explicitly (see k_pass).
 template <int SIZE>
 __device__ __forceinline__ void lds_dma(const char *g, void *lds) {
   if constexpr (SIZE == 4)
@@ -722,10 +722,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Target wavefronts per SIMD of a sweep instantiation: 512 registers per lane
 // divided by the live tile states, the contraction accumulators and a fixed
 // allowance for addresses, coefficients in flight and temporaries.
-// Slabs of a backward tile prefetched into LDS (bit s: 0 checkpoint psi,
-// 1 phi, 2 checkpoint dpsi, 3 dphi).  Complex64 prefetches only the
-// checkpoints: 16 KB of LDS per wavefront at 16 amplitudes leave room for two
-// wavefronts per SIMD.
+// Slabs of a backward tile brought into LDS (bit s: 0 checkpoint psi, 1 phi,
+// 2 checkpoint dpsi, 3 dphi): the checkpoints only for complex64 and for the
+// parity gradient (16 KB per wavefront leave room for two wavefronts per
+// SIMD), all slabs of the next tile for complex128 HVP and dense gradients.
 template <typename R, int NT, int MODE, int OP>
 struct Prefetch {
   static constexpr int mask =
@@ -775,10 +775,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((
   using K = Codes<MODE, NT>;
   extern __shared__ double lds[];
 
-  // Backward passes run one wavefront per block and prefetch slabs of the
-  // next tile into LDS with direct loads (slab s in PFMASK: 0 checkpoint
-  // psi, 1 phi, 2 checkpoint dpsi, 3 dphi); the others are loaded into
-  // registers at the top of the tile.
+  // Backward passes run one wavefront per block and bring the PFMASK slabs
+  // (0 checkpoint psi, 1 phi, 2 checkpoint dpsi, 3 dphi) into LDS with direct
+  // loads: with LRES the current tile's checkpoints, which stay there while
+  // the gates are un-applied in place; otherwise the next tile, prefetched
+  // while the current one is computed from registers.  The other slabs are
+  // loaded into registers at the top of the tile.
   constexpr bool PF = STAGE == ST_BWD;
   constexpr bool LRES = PF && Resident<R, NT, MODE, OP>::value;   // forward states in LDS
   constexpr int DW = int(ES) / 4;                 // dwords per amplitude
