@@ -10,7 +10,12 @@ One step = one evaluation: f, Riemannian gradient of all gates and one
 Hessian-vector product along a seeded tangent direction, summed over all
 2^16 basis states, target columns resident in HBM.
 
-Prints one JSON line (see README section of the design doc for the fields).
+Prints one JSON line: the throughput (evaluations per second) and its
+per-kernel breakdown, the roofline of the dominant kernel (algorithmic HBM
+bytes or flops per launch over its HIP-event time, against the MI355X peaks),
+the complex128 run and the c64 error against it, further workloads (Hessian
+blocks, configuration 4, orbit-reduced and sampled traces, trust-region
+iterations, the serving mix) and the oracle's CPU rate on a bounded sample.
 """
 
 from __future__ import annotations
@@ -247,8 +252,8 @@ def main():
                     help="run a plain 2 GiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the "
-              "multi-GPU sharding of the basis sum is described in DESIGN.md but not run.",
+        print(f"bench.py: runs on exactly one GPU (asked for {args.gpus}); sharding the basis "
+              "sum over several GPUs is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 
