@@ -62,10 +62,11 @@ constexpr int kParityIdx[8] = {0, 3, 12, 15, 5, 6, 9, 10};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Tile qubits per (precision, op): the largest tile whose register footprint
-// keeps the sweep kernel free of scratch spills (states held per lane:
-// cost/apply 1, grad 2, HVP 4).
-int nt_max(int is_double, int op) {
+// Tile qubits per (precision, op, gate class): the largest tile whose
+// register footprint keeps the sweep kernel free of scratch spills (states
+// held per lane: cost/apply 1, grad 2, HVP 4; parity-mode backward sweeps
+// keep the two forward states in LDS instead).
+int nt_max(int is_double, int op, bool parity) {
   if (!is_double) {
     switch (op) {
       case OP_COST: case OP_APPLY: case OP_GRAD: return 5;
@@ -75,14 +76,14 @@ int nt_max(int is_double, int op) {
     switch (op) {
       case OP_COST: case OP_APPLY: return 5;
       case OP_GRAD: return 4;
-      case OP_HVP: return 3;
+      case OP_HVP: return parity ? 4 : 3;
     }
   }
   return 2;
 }
 
-int tile_nt(int kq, int is_double, int op) {
-  const int m = nt_max(is_double, op);
+int tile_nt(int kq, int is_double, int op, bool parity) {
+  const int m = nt_max(is_double, op, parity);
   return kq >= m ? m : 2;
 }
 
@@ -193,7 +194,7 @@ int make_layout(const rq_circuit *c, int32_t op_pub, int32_t dtype, int64_t chun
   L.parity = (c->flags & RQ_PARITY) != 0;
   L.number = (c->flags & RQ_NUMBER) != 0;
   L.kq = L.parity ? c->n_qubits - 1 : c->n_qubits;
-  L.nt = tile_nt(L.kq, L.is_double, op);
+  L.nt = tile_nt(L.kq, L.is_double, op, L.parity);
   L.ne = entries(op, L.parity);
   if (op != OP_APPLY && ((int64_t(1) << (L.kq - L.nt)) * ((chunk + 63) / 64)) >= (int64_t(1) << 31))
     return fail(RQ_EINVAL, "problem too large for one sweep grid (reduce chunk)");

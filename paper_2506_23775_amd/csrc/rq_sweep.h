@@ -729,8 +729,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <typename R, int NT, int MODE, int OP>
 struct Prefetch {
   static constexpr int mask =
-      (sizeof(R) == 4 || (MODE == MODE_PARITY && OP == OP_GRAD)) ? (OP == OP_HVP ? 0x5 : 0x1)
-                                                                 : (OP == OP_HVP ? 0xf : 0x3);
+      (sizeof(R) == 4 || MODE == MODE_PARITY) ? (OP == OP_HVP ? 0x5 : 0x1)
+                                              : (OP == OP_HVP ? 0xf : 0x3);
 };
 
 // Backward passes that keep the forward states (checkpoint psi, dpsi) in LDS
@@ -740,8 +740,15 @@ struct Prefetch {
 // exactly the checkpoint slabs of Prefetch (no look-ahead tile).
 template <typename R, int NT, int MODE, int OP>
 struct Resident {
-  static constexpr bool value =
-      MODE == MODE_PARITY && (OP == OP_GRAD || (OP == OP_HVP && sizeof(R) == 4));
+  static constexpr bool value = MODE == MODE_PARITY && (OP == OP_GRAD || OP == OP_HVP);
+  // the fused last pass too, for the HVP (whose backward half holds four
+  // states); the gradient's last pass peaks in its forward half
+  static constexpr bool last = value && OP == OP_HVP;
+  // LDS per wavefront: the resident states and the contraction accumulators
+  static constexpr int lds_bytes = (OP == OP_HVP ? 2 : 1) * (1 << NT) * 64 * int(2 * sizeof(R)) +
+                                   kMaxGates * (OP == OP_HVP ? 32 : 16) * 8;
+  // two wavefronts per SIMD when 8 of them fit the 160 KB of LDS of a CU
+  static constexpr int waves = lds_bytes <= 20480 ? 2 : 1;
 };
 
 template <typename R, int NT, int MODE, int OP, int STAGE>
@@ -757,7 +764,9 @@ struct Occupancy {
   // Backward-type kernels keep the compiler's own allocation (at two waves per
   // SIMD their register-resident states would spill to scratch memory),
   // except those with LDS-resident forward states.
-  static constexpr int value = (STAGE == ST_BWD && Resident<R, NT, MODE, OP>::value) ? 2
+  static constexpr bool res = STAGE == ST_BWD ? Resident<R, NT, MODE, OP>::value
+                              : STAGE == ST_LAST && Resident<R, NT, MODE, OP>::last;
+  static constexpr int value = res ? Resident<R, NT, MODE, OP>::waves
                                : STAGE != ST_FWD ? 1 : (w < 1 ? 1 : (w > 8 ? 8 : w));
 };
 
@@ -783,10 +792,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((
   // loaded into registers at the top of the tile.
   constexpr bool PF = STAGE == ST_BWD;
   constexpr bool LRES = PF && Resident<R, NT, MODE, OP>::value;   // forward states in LDS
+  // the fused last pass of the HVP keeps them in LDS for its backward half
+  constexpr bool LRESL = STAGE == ST_LAST && Resident<R, NT, MODE, OP>::last;
   constexpr int DW = int(ES) / 4;                 // dwords per amplitude
   constexpr int PFMASK = Prefetch<R, NT, MODE, OP>::mask;
   constexpr int NPF = __builtin_popcount(PFMASK);
-  constexpr int PF_BYTES = PF ? NPF * NA * 64 * int(ES) : 0;
+  constexpr int PF_BYTES = (PF || LRESL) ? NPF * NA * 64 * int(ES) : 0;
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
@@ -1039,6 +1050,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((
         if constexpr (HV) dph[i] = zero;
       });
       facc += (double)hre;
+      if constexpr (LRESL) {  // forward states -> LDS for the backward half
+        static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+          sps[CV(I) * 64 + lane] = ps[CV(I)];
+          if constexpr (HV) sdps[CV(I) * 64 + lane] = dps[CV(I)];
+        });
+      }
     }
 
     if constexpr (NEEDB) {
@@ -1048,7 +1065,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((
         R tp[NE];
         static_for<0, NE>([&](auto E) __attribute__((always_inline)) { tp[CV(E)] = R(0); });
         dispatch<0, K::n>(gate_code(MODE, NT, gr, pi), [&](auto CC) __attribute__((always_inline)) {
-          if constexpr (LRES)
+          if constexpr (LRES || LRESL)
             bwd_gate_l<R, NT, MODE, HV, CV(CC), NE>(sps, sdps, lane, ph, dph, co, tp);
           else
             bwd_gate<R, NT, MODE, HV, CV(CC), NE>(ps, dps, ph, dph, co, tp);
@@ -1096,7 +1113,8 @@ static int launch_one(const PassArgs &a, int grid, void *stream) {
   constexpr bool NEEDB = STAGE != ST_FWD && (OP == OP_GRAD || OP == OP_HVP);
   constexpr int NT1 = MODE == MODE_DENSE ? 32 : 16;
   constexpr int NE = HV ? 2 * NT1 : NT1;
-  if constexpr (STAGE == ST_BWD) {
+  constexpr bool LRESL = STAGE == ST_LAST && Resident<R, NT, MODE, OP>::last;
+  if constexpr (STAGE == ST_BWD || LRESL) {
     // one wavefront per block: grid * 4 blocks of 64 threads give the same
     // wavefronts (and slot indices) as grid blocks of 256 threads
     constexpr int NPF = __builtin_popcount(Prefetch<R, NT, MODE, OP>::mask);
@@ -1138,11 +1156,13 @@ static int launch_mode(int op, int stage, const PassArgs &a, int grid, void *s) 
   return -2;
 }
 
-template <typename R, int NT, bool COST, bool GRAD, bool HVP>
+// HVPD / HVPP: HVP instantiations for dense / parity gates (their tile sizes
+// differ in complex128).
+template <typename R, int NT, bool COST, bool GRAD, bool HVPD, bool HVPP>
 static int launch_nt(int mode, int op, int stage, const PassArgs &a, int grid, void *s) {
   return mode == MODE_DENSE
-             ? launch_mode<R, NT, MODE_DENSE, COST, GRAD, HVP>(op, stage, a, grid, s)
-             : launch_mode<R, NT, MODE_PARITY, COST, GRAD, HVP>(op, stage, a, grid, s);
+             ? launch_mode<R, NT, MODE_DENSE, COST, GRAD, HVPD>(op, stage, a, grid, s)
+             : launch_mode<R, NT, MODE_PARITY, COST, GRAD, HVPP>(op, stage, a, grid, s);
 }
 
 }  // namespace rqk

@@ -3,6 +3,6 @@
 
 namespace rqk {
 int launch_pass_f32_nt5(int mode, int op, int stage, const PassArgs &a, int grid, void *s) {
-  return launch_nt<float, 5, true, true, false>(mode, op, stage, a, grid, s);
+  return launch_nt<float, 5, true, true, false, false>(mode, op, stage, a, grid, s);
 }
 }  // namespace rqk

@@ -3,6 +3,6 @@
 
 namespace rqk {
 int launch_pass_f64_nt5(int mode, int op, int stage, const PassArgs &a, int grid, void *s) {
-  return launch_nt<double, 5, true, false, false>(mode, op, stage, a, grid, s);
+  return launch_nt<double, 5, true, false, false, false>(mode, op, stage, a, grid, s);
 }
 }  // namespace rqk
