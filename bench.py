@@ -454,6 +454,8 @@ def main():
         out["c64_rel_error_vs_c128"] = {k: float(f"{v:.3e}") for k, v in err.items()}
         dom128 = max(r128["prof"].items(), key=lambda kv: kv[1]["ms"])[0]
         out["roofline_c128"] = roofline(r128["prof"], dom128)
+        if args.chunk128 == 2048:
+            out["roofline_c128"]["traffic"] = measured_traffic(f"c128:{dom128[0]}/{dom128[1]}")
 
     if args.tr_iters > 0:
         # configuration 2 (k = 12, 30 gates): full Riemannian trust-region
