@@ -148,11 +148,12 @@ def measured_traffic(kernel_key):
     if not (os.path.exists(prof) and os.path.exists(src)):
         return None
     sha = code_hash(src)
+    import re
     vals = {}
     for line in open(prof):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip()
+        m = re.match(r"(traffic_bytes_per_launch\[[^\]]+\]|code_sha256_16):\s*(\S+)", line)
+        if m:
+            vals[m.group(1)] = m.group(2)
     if vals.get("code_sha256_16") != sha:
         return None
     v = vals.get(f"traffic_bytes_per_launch[{kernel_key}]")
