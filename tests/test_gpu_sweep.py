@@ -109,6 +109,34 @@ def test_parity_sectors(rq, dtype, k, layers, shared):
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("k", [4, 5])
+def test_parity_small_tiles(rq, dtype, k):
+    """Parity sectors of 2^3 and 2^4 rows: below the 4-qubit tile (2-qubit
+    tiles) and exactly one 4-qubit tile with no tile-index bits, with a
+    parity-conserving target made of random parity gates."""
+    rng = np.random.default_rng([19, k, dtype])
+    # open-chain brick wall (any k): bonds (q, q+1), even bonds then odd ones
+    pairs = [(q, q + 1) for layer in range(3) for q in range(layer % 2, k - 1, 2)]
+    param_of = np.arange(len(pairs), dtype=np.int32)
+    gates = w.parity_haar_gates(rng, len(pairs))
+    direction = w.tangent_direction(rng, gates, parity=True)
+    U = np.eye(1 << k, dtype=complex)
+    for layer in range(6):
+        for q in range(layer % 2, k - 1, 2):
+            U = O.apply_gate(U, k, (q, q + 1), w.parity_haar_gates(rng, 1)[0])
+    circ = rq.Circuit(k, pairs, param_of=param_of, parity=True)
+    tgt = rq.Target.from_dense(U, dtype, parity=True)
+    ref = oracle_eval(k, pairs, gates, param_of, direction, U, None, parity=True)
+    _check(rq.rq_hvp(circ, tgt, gates, direction), ref, dtype, "parity full")
+    _check(rq.rq_grad(circ, tgt, gates), ref, dtype, "parity grad")
+    n = 1 << (k - 1)
+    cols = sector_full_index(k, 1, np.arange(1, n))
+    ref = oracle_eval(k, pairs, gates, param_of, direction, U[:, cols], cols, parity=True)
+    _check(rq.rq_hvp(circ, tgt, gates, direction, range=(1, 1, n - 1), chunk=64), ref, dtype,
+           "sector 1 ragged")
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
 def test_apply_circuit(rq, dtype):
     import torch
     rng = np.random.default_rng([10, dtype])
