@@ -723,9 +723,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // divided by the live tile states, the contraction accumulators and a fixed
 // allowance for addresses, coefficients in flight and temporaries.
 // Slabs of a backward tile brought into LDS (bit s: 0 checkpoint psi, 1 phi,
-// 2 checkpoint dpsi, 3 dphi): the checkpoints only for complex64 and for the
-// parity gradient (16 KB per wavefront leave room for two wavefronts per
-// SIMD), all slabs of the next tile for complex128 HVP and dense gradients.
+// 2 checkpoint dpsi, 3 dphi): the checkpoints only for complex64 and for
+// parity gates (where they stay resident, see Resident), all slabs of the
+// next tile for complex128 with dense gates.
 template <typename R, int NT, int MODE, int OP>
 struct Prefetch {
   static constexpr int mask =
@@ -736,8 +736,10 @@ struct Prefetch {
 // Backward passes that keep the forward states (checkpoint psi, dpsi) in LDS
 // for the whole tile -- loaded there by direct global->LDS loads, un-applied
 // block by block in place -- so that only phi (+dphi) and the contraction
-// partials occupy registers and two wavefronts fit per SIMD.  Their LDS holds
-// exactly the checkpoint slabs of Prefetch (no look-ahead tile).
+// partials occupy registers: two wavefronts per SIMD where the LDS allows it
+// (complex64 HVP, gradients), else one, which still lets complex128 HVP run
+// 4-qubit tiles without spills.  Their LDS holds exactly the checkpoint slabs
+// of Prefetch (no look-ahead tile).
 template <typename R, int NT, int MODE, int OP>
 struct Resident {
   static constexpr bool value = MODE == MODE_PARITY && (OP == OP_GRAD || OP == OP_HVP);
