@@ -127,7 +127,8 @@ __global__ __launch_bounds__(kBlock) void k_hess_pass(const HessArgs A) {
         ph[CV(I)] = ok ? v : zero;
       });
       R tp[NE];
-      static_for<0, NE>([&](auto E) __attribute__((always_inline)) { tp[CV(E)] = R(0); });
+      // -0: the first fma into each partial folds into a multiply
+      static_for<0, NE>([&](auto E) __attribute__((always_inline)) { tp[CV(E)] = R(-0.0); });
       dispatch<0, K::n>(gate_code(MODE, NT, gr, pi), [&](auto CC) __attribute__((always_inline)) {
         contract_gate<R, NT, MODE, CV(CC), NE>(ps, ph, tp);
         fwd_gate<R, NT, MODE, false, CV(CC)>(ps, ps, co);

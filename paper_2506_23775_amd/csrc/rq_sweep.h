@@ -992,13 +992,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((
       // tile's LDS accesses completed), phi (+dphi) into registers
       wait_lgkm0();
       prefetch(item);
+      // padding lanes (ragged chunk) read a clamped copy of a valid column:
+      // finite, and every product they enter has a zeroed psi or dpsi factor
       static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
-        const cx<R> p = pf_read(ic<1>{}, I, rowb, voff);
-        ph[CV(I)] = ok ? p : zero;
-        if constexpr (HV) {
-          const cx<R> pd = pf_read(ic<3>{}, I, rowb, voff);
-          dph[CV(I)] = ok ? pd : zero;
-        }
+        ph[CV(I)] = pf_read(ic<1>{}, I, rowb, voff);
+        if constexpr (HV) dph[CV(I)] = pf_read(ic<3>{}, I, rowb, voff);
       });
       wait_vmcnt<0>();
       if (!ok) {  // padding columns of a ragged chunk: zero states
@@ -1065,7 +1063,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((
         const GateRef gr = A.gates[g];
         ccoef_t<R> *co = coef + int64_t(gr.inst) * kCoefStride;
         R tp[NE];
-        static_for<0, NE>([&](auto E) __attribute__((always_inline)) { tp[CV(E)] = R(0); });
+        // -0 is the exact additive identity: the first fma into each
+        // partial folds into a plain multiply, with no zeroing moves (not in
+        // the dense fused last pass, whose allocation then spills)
+        constexpr R tp0 = (STAGE == ST_LAST && MODE == MODE_DENSE) ? R(0) : R(-0.0);
+        static_for<0, NE>([&](auto E) __attribute__((always_inline)) { tp[CV(E)] = tp0; });
         dispatch<0, K::n>(gate_code(MODE, NT, gr, pi), [&](auto CC) __attribute__((always_inline)) {
           if constexpr (LRES || LRESL)
             bwd_gate_l<R, NT, MODE, HV, CV(CC), NE>(sps, sdps, lane, ph, dph, co, tp);
