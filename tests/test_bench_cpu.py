@@ -1,0 +1,40 @@
+"""Host-side checks of bench.py: the one-GPU contract, the comment-blind code
+hash that keys stored profiler measurements, and the lookup of measured HBM
+traffic per launch."""
+
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_code_hash_ignores_comments_and_whitespace(tmp_path):
+    a = tmp_path / "a.h"
+    b = tmp_path / "b.h"
+    c = tmp_path / "c.h"
+    a.write_text("int f(int x) { return x + 1; }\n")
+    b.write_text("// increment\nint f(int x) {\n  /* one */ return x + 1;  // done\n}\n")
+    c.write_text("int f(int x) { return x + 2; }\n")
+    assert bench.code_hash(str(a)) == bench.code_hash(str(b))
+    assert bench.code_hash(str(a)) != bench.code_hash(str(c))
+
+
+def test_measured_traffic_lookup():
+    assert bench.measured_traffic("no/such") is None
+    for key in ("hvp/bwd", "c128:hvp/bwd"):
+        v = bench.measured_traffic(key)
+        # None when the sweep kernel changed since the counters were taken;
+        # otherwise at least the 6 GiB the pass must move (4 slabs read, 2
+        # written, 1 GiB each at the benchmark's chunk)
+        assert v is None or v >= 0.9 * 6 * 2**30, (key, v)
