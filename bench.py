@@ -232,7 +232,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chunk", type=int, default=4096)
-    ap.add_argument("--chunk128", type=int, default=2048)
+    ap.add_argument("--chunk128", type=int, default=4096)
     ap.add_argument("--trotter-steps", type=int, default=200)
     ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -455,7 +455,7 @@ def main():
         out["c64_rel_error_vs_c128"] = {k: float(f"{v:.3e}") for k, v in err.items()}
         dom128 = max(r128["prof"].items(), key=lambda kv: kv[1]["ms"])[0]
         out["roofline_c128"] = roofline(r128["prof"], dom128)
-        if args.chunk128 == 2048:
+        if args.chunk128 == 4096:
             out["roofline_c128"]["traffic"] = measured_traffic(f"c128:{dom128[0]}/{dom128[1]}")
 
     if args.tr_iters > 0:
