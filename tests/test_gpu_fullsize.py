@@ -30,7 +30,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = {0: dict(f=1e-12, v=1e-10), 1: dict(f=1e-5, v=2e-5)}   # RQ_C128, RQ_C64
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_eval.json")
-BENCH_CHUNK = {1: 4096, 0: 2048}        # chunk sizes the benchmark uses (c64, c128)
+BENCH_CHUNK = {1: 4096, 0: 4096}        # chunk sizes the benchmark uses (c64, c128)
 PIDX = [0, 3, 12, 15, 5, 6, 9, 10]
 
 
