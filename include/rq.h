@@ -172,8 +172,10 @@ typedef struct rq_exec {
   uint32_t reserved;
 } rq_exec;
 
-/* Bytes of workspace needed for op (RQ_OP_*) with states of dtype and the
- * given chunk.  Returns 0 for invalid arguments (see rq_last_error). */
+/* Bytes of workspace needed for op (RQ_OP_COST, RQ_OP_GRAD, RQ_OP_HVP,
+ * RQ_OP_APPLY) with states of dtype and the given chunk.  Returns 0 for
+ * invalid arguments (see rq_last_error), including RQ_OP_HESS, whose
+ * workspace rq_hess_workspace_bytes gives. */
 size_t rq_workspace_bytes(const rq_circuit *circuit, int32_t op, int32_t dtype,
                           int64_t chunk);
 
@@ -316,12 +318,22 @@ int rq_plan_passes(const rq_circuit *circuit, int32_t op, int32_t dtype,
  * k = 3*op + stage for k < 12 (op: 0 cost, 1 grad, 2 HVP, 3 apply; stage:
  * 0 forward pass, 1 fused last pass, 2 backward pass), and k = 12 Hessian
  * hole-array sweep, 13 Hessian per-gate state passes, 14 gate-hole
- * application, the summed kernel time in ms, the number of launches, and the
- * algorithmic HBM bytes and flops of those launches (arrays of 15 entries
- * each, any may be NULL); then it resets. */
+ * application, 15 rq_stream_copy, the summed kernel time in ms, the number
+ * of launches, and the algorithmic HBM bytes and flops of those launches
+ * (arrays of 16 entries each, any may be NULL); then it resets. */
 int rq_profile_enable(int on);
 int rq_profile_read(double *ms, int64_t *launches, double *bytes,
                     double *flops);
+
+/* Diagnostics: streaming device-to-device copy of `bytes` bytes (a multiple
+ * of 16; both pointers 16-byte aligned) by a hand-written kernel in which
+ * every thread moves `unroll` (1, 2, 4 or 8) 16-byte vectors per grid-stride
+ * iteration, all loads before the stores; `blocks` workgroups of 256 threads
+ * (0: 2048).  The buffers must not overlap.  Measures the practical HBM
+ * read+write rate that the streaming sweep kernels are compared with.
+ * Stream-ordered like every call; RQ_EINVAL on bad arguments. */
+int rq_stream_copy(void *dst, const void *src, size_t bytes, int32_t unroll, int32_t blocks,
+                   void *stream);
 
 const char *rq_strerror(int status);
 const char *rq_last_error(void);

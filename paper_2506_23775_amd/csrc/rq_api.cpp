@@ -425,7 +425,7 @@ double flops_per_amp_gate(int op, int stage, bool parity) {
 
 // Profiled launch: HIP events around launch() on stream s when profiling is
 // on; kind, algorithmic bytes and flops are recorded with the events.
-constexpr int kProfKinds = 15;
+constexpr int kProfKinds = 16;
 template <typename F>
 int prof_launch(hipStream_t s, int kind, double bytes, double flops, F &&launch) {
   ProfRec r{};
@@ -1020,6 +1020,18 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
 
 }  // namespace
 
+namespace rqk {
+// Entry points for other translation units of the library (the static-
+// scratch variant in rq_static.hip): the sweep call of rq_cost / rq_grad /
+// rq_hvp with a caller-chosen workspace, and the thread-local error slot.
+int sweep_call(const rq_circuit *c, const rq_target *t, const double *gates, const double *dir,
+               const rq_range *range, const rq_exec *ex, int32_t op_pub, double *d_f,
+               double *d_egrad, double *d_rgrad, double *d_ehvp, double *d_rhvp) {
+  return run_sweep(c, t, gates, dir, range, ex, op_pub, d_f, d_egrad, d_rgrad, d_ehvp, d_rhvp);
+}
+int api_fail(int code, const char *msg) { return fail(code, msg); }
+}  // namespace rqk
+
 extern "C" {
 
 size_t rq_hess_workspace_bytes(const rq_circuit *circuit, int32_t dtype, int64_t chunk) {
@@ -1135,11 +1147,11 @@ int rq_hess_blocks(const rq_circuit *circuit, const rq_target *target, const dou
 
 size_t rq_workspace_bytes(const rq_circuit *circuit, int32_t op, int32_t dtype, int64_t chunk) {
   if (op == RQ_OP_HESS) {
-    g_err = "rq_workspace_bytes: RQ_OP_HESS uses rq_hess_workspace_bytes";
+    g_err = "rq_workspace_bytes: the Hessian workspace is sized by rq_hess_workspace_bytes";
+    return 0;
   }
   Layout L;
-  if (make_layout(circuit, op == RQ_OP_HESS ? RQ_OP_GRAD : op, dtype, op == RQ_OP_APPLY ? 64 : chunk, L))
-    return 0;
+  if (make_layout(circuit, op, dtype, op == RQ_OP_APPLY ? 64 : chunk, L)) return 0;
   return L.total;
 }
 
@@ -1254,6 +1266,23 @@ int rq_profile_read(double *ms, int64_t *launches, double *bytes, double *flops)
     g_event_pool.push_back(r.b);
   }
   return st;
+}
+
+int rq_stream_copy(void *dst, const void *src, size_t bytes, int32_t unroll, int32_t blocks,
+                   void *stream) {
+  if (!dst || !src) return fail(RQ_EINVAL, "rq_stream_copy: NULL pointer");
+  if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src) | bytes) & 15)
+    return fail(RQ_EINVAL, "rq_stream_copy: pointers and size must be multiples of 16 bytes");
+  if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8)
+    return fail(RQ_EINVAL, "rq_stream_copy: unroll must be 1, 2, 4 or 8");
+  if (blocks < 0 || blocks > (1 << 20)) return fail(RQ_EINVAL, "rq_stream_copy: blocks out of range");
+  if (bytes == 0) return RQ_OK;
+  const int b = blocks ? blocks : 2048;
+  return prof_launch(static_cast<hipStream_t>(stream), 15, 2.0 * double(bytes), 0.0, [&] {
+           return launch_stream_copy(dst, src, int64_t(bytes), unroll, b, stream);
+         })
+             ? fail(RQ_EHIP, "rq_stream_copy: launch failed")
+             : RQ_OK;
 }
 
 const char *rq_strerror(int status) {

@@ -64,12 +64,15 @@ struct PassArgs {
   GateRef gates[kMaxGates];
 };
 
-// Host-side launchers (defined in rq_kernels.hip).
+// Host-side launchers (defined in rq_launch.hip and the sweep
+// instantiation units).
 int launch_pass(int is_double, int nt, int mode, int op, int stage,
                 const PassArgs &a, int grid, void *stream);
 int launch_reduce(const double *slots, int n_inst, int ne, int nslots,
                   double *out, void *stream);
 int launch_zero(double *p, int64_t n, void *stream);
+int launch_stream_copy(void *dst, const void *src, int64_t bytes, int unroll, int blocks,
+                       void *stream);
 int launch_post(int op, int parity, int accumulate, int n_params, int n_inst, const int32_t *param_of,
                 const double *tsum, int ne, const double *fslots, int nslots,
                 const double *gates64, const double *dir64, double *d_f,

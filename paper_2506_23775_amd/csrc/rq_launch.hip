@@ -72,6 +72,42 @@ int launch_zero(double *p, int64_t n, void *s) {
 }
 
 // ----------------------------------------------------------------------------
+// Streaming device copy (diagnostic: the practical HBM read+write rate the
+// sweep kernels are compared with).  Each thread moves UNROLL 16-byte
+// vectors per iteration, all loads issued before the stores; the grid
+// strides over the buffer.
+// ----------------------------------------------------------------------------
+template <int UNROLL>
+__global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ src,
+                                                     uint4 *__restrict__ dst, int64_t n16) {
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  for (; i + (UNROLL - 1) * stride < n16; i += UNROLL * stride) {
+    uint4 v[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) v[u] = src[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) dst[i + u * stride] = v[u];
+  }
+  for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+int launch_stream_copy(void *dst, const void *src, int64_t bytes, int unroll, int blocks,
+                       void *s) {
+  const int64_t n16 = bytes / 16;
+  const uint4 *a = static_cast<const uint4 *>(src);
+  uint4 *b = static_cast<uint4 *>(dst);
+  switch (unroll) {
+    case 1: hipLaunchKernelGGL(k_stream_copy<1>, dim3(blocks), dim3(256), 0, (hipStream_t)s, a, b, n16); break;
+    case 2: hipLaunchKernelGGL(k_stream_copy<2>, dim3(blocks), dim3(256), 0, (hipStream_t)s, a, b, n16); break;
+    case 4: hipLaunchKernelGGL(k_stream_copy<4>, dim3(blocks), dim3(256), 0, (hipStream_t)s, a, b, n16); break;
+    case 8: hipLaunchKernelGGL(k_stream_copy<8>, dim3(blocks), dim3(256), 0, (hipStream_t)s, a, b, n16); break;
+    default: return -2;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ----------------------------------------------------------------------------
 // Riemannian post-processing in FP64 (Sec. "Riemannian optimization"):
 //   egrad = -conj(T)  (gradient convention d_x f + i d_y f for f = -Re h),
 //   rgrad = P_G(egrad),  P_V Y = (Y - V Y^dagger V) / 2,

@@ -63,7 +63,7 @@ EXPORTS = ["rq_workspace_bytes", "rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks
            "rq_hess_workspace_bytes", "rq_apply_circuit", "rq_tr_step", "rq_tr_accept",
            "rq_tangent_coords", "rq_tr_workspace_bytes", "rq_tr_solve",
            "rq_tangent_basis", "rq_plan_passes", "rq_profile_enable", "rq_profile_read",
-           "rq_strerror", "rq_last_error"]
+           "rq_stream_copy", "rq_strerror", "rq_last_error"]
 
 
 def lib():
@@ -102,11 +102,12 @@ def lib():
     L.rq_plan_passes.argtypes = [C.POINTER(_Circuit), C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     L.rq_profile_enable.argtypes = [C.c_int]
     L.rq_profile_read.argtypes = [dp, C.POINTER(C.c_int64), dp, dp]
+    L.rq_stream_copy.argtypes = [P, P, C.c_size_t, C.c_int32, C.c_int32, P]
     L.rq_strerror.restype = C.c_char_p
     L.rq_last_error.restype = C.c_char_p
     for name in ["rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks", "rq_apply_circuit",
                  "rq_tr_step", "rq_tr_accept", "rq_tangent_basis", "rq_plan_passes",
-                 "rq_tangent_coords", "rq_tr_solve",
+                 "rq_tangent_coords", "rq_tr_solve", "rq_stream_copy",
                  "rq_profile_enable", "rq_profile_read"]:
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -265,13 +266,20 @@ class Workspace:
 _ws_cache = {}
 
 
-def _workspace(nbytes: int, key=None) -> Workspace:
-    key = key or (torch.cuda.current_device(),)
-    ws = _ws_cache.get(key)
+def _workspace(nbytes: int, stream, key=()) -> Workspace:
+    """Default workspace of calls that pass none: one cached buffer per
+    (device, stream, key).  Calls on one stream run in order, so they may
+    share it; calls on different streams never do (concurrent calls need
+    distinct workspaces).  A larger request replaces the stream's buffer;
+    the old one is released to torch's caching allocator on the current
+    stream, which orders its reuse after the work already enqueued there."""
+    k = (torch.cuda.current_device(), int(stream.cuda_stream)) + tuple(key)
+    ws = _ws_cache.get(k)
     if ws is None or ws.nbytes < nbytes:
-        _ws_cache.pop(key, None)
-        ws = Workspace(nbytes)
-        _ws_cache[key] = ws
+        _ws_cache.pop(k, None)
+        with torch.cuda.stream(stream):
+            ws = Workspace(nbytes)
+        _ws_cache[k] = ws
     return ws
 
 
@@ -303,10 +311,10 @@ def _exec(circuit: Circuit, op: int, dtype: int, chunk, workspace, stream, flags
         need = L.rq_workspace_bytes(C.byref(circuit._c), op, dtype, chunk)
     if need == 0:
         raise RQError(RQ_EINVAL, "rq_workspace_bytes")
-    ws = workspace if workspace is not None else _workspace(need)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    ws = workspace if workspace is not None else _workspace(need, s)
     if ws.nbytes < need:
         raise RuntimeError(f"workspace too small: {ws.nbytes} < {need}")
-    s = stream if stream is not None else torch.cuda.current_stream()
     return _Exec(ws.ptr, ws.nbytes, chunk, s.cuda_stream, flags, 0), ws
 
 
@@ -419,8 +427,8 @@ def rq_apply_circuit(circuit: Circuit, gates, states: torch.Tensor, dtype: Optio
     need = L.rq_workspace_bytes(C.byref(circuit._c), RQ_OP_APPLY, dtype, 0)
     if need == 0:
         raise RQError(RQ_EINVAL, "rq_workspace_bytes")
-    ws = workspace if workspace is not None else _workspace(need, key=("apply",))
     s = stream if stream is not None else torch.cuda.current_stream()
+    ws = workspace if workspace is not None else _workspace(need, s, key=("apply",))
     ex = _Exec(ws.ptr, ws.nbytes, 0, s.cuda_stream)
     _check(L.rq_apply_circuit(C.byref(circuit._c), _dptr(g), states.data_ptr(), states.shape[1],
                               states.stride(0), dtype, sector, C.byref(ex)), "rq_apply_circuit")
@@ -468,6 +476,19 @@ def rq_tr_accept(f0, f1, model_decrease, delta, delta_bar, eta_norm):
     return nd.value, bool(acc.value), rho.value
 
 
+def rq_stream_copy(dst: torch.Tensor, src: torch.Tensor, unroll: int = 4, blocks: int = 0,
+                   stream=None):
+    """Diagnostic streaming copy of src into dst (same byte size, a multiple
+    of 16) by librq's hand-written copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous with the same byte size")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().rq_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, int(unroll), int(blocks),
+                                s.cuda_stream), "rq_stream_copy")
+    return dst
+
+
 def rq_tangent_coords(gates, Y, parity=False) -> np.ndarray:
     """Coordinates Re Tr[(G_p A_mu)^dagger Y_p] in the tangent basis (host)."""
     G = _gates_host(gates)
@@ -491,8 +512,8 @@ def rq_tr_solve(circuit: Circuit, target: Target, gates, max_iter: int = 20, gto
     need = L.rq_tr_workspace_bytes(C.byref(circuit._c), target.dtype, chunk)
     if need == 0:
         raise RQError(RQ_EINVAL, "rq_tr_workspace_bytes")
-    ws = workspace if workspace is not None else _workspace(need, key=("tr",))
     s = stream if stream is not None else torch.cuda.current_stream()
+    ws = workspace if workspace is not None else _workspace(need, s, key=("tr",))
     ex = _Exec(ws.ptr, ws.nbytes, chunk, s.cuda_stream)
     hist = np.zeros((max(1, max_iter), 6))
     n = C.c_int32(0)
@@ -502,25 +523,42 @@ def rq_tr_solve(circuit: Circuit, target: Target, gates, max_iter: int = 20, gto
     return G, hist[:n.value]
 
 
+def apply_workspace(k: int, gate_list, dtype: int, parity: bool = False) -> Workspace:
+    """Workspace for rq_apply_circuit with a gate list (its gate
+    coefficients), for callers that run several applications concurrently on
+    different streams and must not share one."""
+    circ = Circuit(k, [p for p, _ in gate_list], parity=parity)
+    need = lib().rq_workspace_bytes(C.byref(circ._c), RQ_OP_APPLY, dtype, 0)
+    if need == 0:
+        raise RQError(RQ_EINVAL, "rq_workspace_bytes")
+    return Workspace(need)
+
+
 def build_trotter_target(k: int, gate_list, dtype: int = RQ_C128, parity: bool = True,
-                         device="cuda") -> Target:
+                         device="cuda", workspace=None, stream=None) -> Target:
     """Target columns U|j> for every basis state, built on the device by
     applying a gate list (e.g. a Trotter circuit) to the identity columns with
-    rq_apply_circuit.  Parity mode returns the two sector blocks."""
+    rq_apply_circuit.  Parity mode returns the two sector blocks.  The work is
+    enqueued on ``stream`` (default: the current stream) with ``workspace``
+    (default: the stream's cached apply workspace)."""
     pairs = [p for p, _ in gate_list]
     gates = np.stack([G for _, G in gate_list])
     circ = Circuit(k, pairs, parity=parity)
     td = torch_dtype(dtype)
-    if parity:
-        n = 1 << (k - 1)
-        ref = torch.zeros((2, n, n), dtype=td, device=device)
-        for p in (0, 1):
-            ref[p].fill_diagonal_(1.0)
-            rq_apply_circuit(circ, gates, ref[p], dtype=dtype, sector=p)
-    else:
-        n = 1 << k
-        ref = torch.eye(n, dtype=td, device=device)
-        rq_apply_circuit(circ, gates, ref, dtype=dtype, sector=-1)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(s):
+        if parity:
+            n = 1 << (k - 1)
+            ref = torch.zeros((2, n, n), dtype=td, device=device)
+            for p in (0, 1):
+                ref[p].fill_diagonal_(1.0)
+                rq_apply_circuit(circ, gates, ref[p], dtype=dtype, sector=p, workspace=workspace,
+                                 stream=s)
+        else:
+            n = 1 << k
+            ref = torch.eye(n, dtype=td, device=device)
+            rq_apply_circuit(circ, gates, ref, dtype=dtype, sector=-1, workspace=workspace,
+                             stream=s)
     return Target(ref, dtype, parity)
 
 
@@ -642,15 +680,16 @@ def rq_profile_enable(on: bool = True):
 def rq_profile_read():
     """Per (op, stage) kernel time (ms), launches, algorithmic bytes, flops
     since the last read (HIP events on the launch streams)."""
-    ms = np.zeros(15)
-    n = np.zeros(15, dtype=np.int64)
-    by = np.zeros(15)
-    fl = np.zeros(15)
+    ms = np.zeros(16)
+    n = np.zeros(16, dtype=np.int64)
+    by = np.zeros(16)
+    fl = np.zeros(16)
     _check(lib().rq_profile_read(_dptr(ms), n.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(by),
                                  _dptr(fl)), "rq_profile_read")
     out = {}
-    hess = {12: ("hess", "sweep"), 13: ("hess", "states"), 14: ("hess", "hole")}
-    for i in range(15):
+    hess = {12: ("hess", "sweep"), 13: ("hess", "states"), 14: ("hess", "hole"),
+            15: ("copy", "stream")}
+    for i in range(16):
         if n[i]:
             key = (OPS[i // 3], STAGES[i % 3]) if i < 12 else hess[i]
             out[key] = dict(ms=float(ms[i]), launches=int(n[i]), bytes=float(by[i]),

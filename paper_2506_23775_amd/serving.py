@@ -137,7 +137,10 @@ class GpuPayload:
     circuit: object                # rq.Circuit
     gates: np.ndarray
     direction: Optional[np.ndarray]
-    make_target: Callable          # () -> rq.Target on the device (called at admission)
+    # (state) -> rq.Target on the device, called at admission on the
+    # request's stream; whatever device memory its enqueued work still uses
+    # (e.g. an apply workspace) is kept in the request's state dict
+    make_target: Callable
     target_bytes: int
 
 
@@ -176,7 +179,7 @@ class GpuExecutor:
         st = req.state
         st["stream"] = torch.cuda.Stream()
         with torch.cuda.stream(st["stream"]):
-            st["target"] = pl.make_target()
+            st["target"] = pl.make_target(st)
             c = pl.circuit
             ws = rq.lib().rq_workspace_bytes(rq.C.byref(c._c), self.OPS[req.op], self.dtype,
                                              self._chunk_cols(req))
@@ -217,12 +220,16 @@ class GpuExecutor:
             ev.record(s)
         st["event"] = ev
 
-    def wait_any(self, active):
+    def wait_any(self, active, poll_s: float = 1e-4):
+        """Return at once if any active request's stream is idle, else after
+        a short sleep: the loop then polls again, admits arrivals and feeds
+        whichever stream went idle first (blocking on one request's event
+        would hold up the others and every new arrival)."""
         for req in active:
             ev = req.state.get("event")
-            if ev is not None and not ev.query():
-                ev.synchronize()
+            if ev is None or ev.query():
                 return
+        time.sleep(poll_s)
 
     def finish(self, req) -> dict:
         st = req.state
@@ -231,21 +238,23 @@ class GpuExecutor:
         res = {"f": float(outs[0][0])}
         for n, o in zip(names[1:], outs[1:]):
             res[n] = o[..., 0] + 1j * o[..., 1]
-        for key in ("target", "ws", "out", "event", "stream"):
+        for key in ("target", "ws", "apply_ws", "out", "event", "stream"):
             st.pop(key, None)
         return res
 
 
 def make_gpu_request(req_desc: dict, dtype: int, trotter_steps: int = 20,
-                     parity: bool = False) -> Request:
+                     parity: bool = False, dense_max_k: int = 12) -> Request:
     """Request from a configuration-5 descriptor: Hubbard target of k qubits,
     brick wall of the given depth with Haar gates.  Targets are dense
-    exp(-iHt) for k <= 12 (uploaded) and a Strang Trotter circuit applied on
-    the device for larger k."""
+    exp(-iHt) for k <= dense_max_k (uploaded) and a Strang Trotter circuit
+    applied on the device for larger k, with an apply workspace of the
+    request's own (concurrent target builds never share gate coefficients)."""
     import workloads as w
 
     from . import rq
-    prob = w.configs.request_problem(req_desc, trotter_steps=trotter_steps)
+    prob = w.configs.request_problem(req_desc, trotter_steps=trotter_steps,
+                                     dense_max_k=dense_max_k)
     k = prob.k
     circ = rq.Circuit(k, prob.pairs, param_of=prob.param_of)
     esize = 16 if dtype == rq.RQ_C128 else 8
@@ -254,13 +263,15 @@ def make_gpu_request(req_desc: dict, dtype: int, trotter_steps: int = 20,
     if prob.U_ref is not None:
         U = prob.U_ref
 
-        def make_target():
+        def make_target(state):
             return rq.Target.from_dense(U, dtype)
     else:
         gl = prob.trotter
 
-        def make_target():
-            return rq.build_trotter_target(k, gl, dtype=dtype, parity=False)
+        def make_target(state):
+            state["apply_ws"] = rq.apply_workspace(k, gl, dtype)
+            return rq.build_trotter_target(k, gl, dtype=dtype, parity=False,
+                                           workspace=state["apply_ws"])
 
     pl = GpuPayload(circ, prob.gates, prob.direction if req_desc["op"] == "hvp" else None,
                     make_target, tbytes)

@@ -65,6 +65,12 @@ def test_invalid_arguments(rq):
     assert L.rq_workspace_bytes(C.byref(c._c), rq.RQ_OP_GRAD, 7, 64) == 0
     c = _circ(rq, 3, [(0, 1)], parity=True)           # parity needs k >= 4
     assert L.rq_workspace_bytes(C.byref(c._c), rq.RQ_OP_GRAD, rq.RQ_C128, 64) == 0
+    # the Hessian workspace has its own sizing call: 0 and a message, never
+    # the (too small) gradient layout
+    c = _circ(rq, 4, [(0, 1), (1, 2)])
+    assert L.rq_workspace_bytes(C.byref(c._c), rq.RQ_OP_HESS, rq.RQ_C128, 64) == 0
+    assert b"rq_hess_workspace_bytes" in L.rq_last_error()
+    assert L.rq_hess_workspace_bytes(C.byref(c._c), rq.RQ_C128, 64) > 0
 
 
 def test_singular_gate_rejected_before_any_device_work(rq):

@@ -133,9 +133,9 @@ def serving_requests(n_requests: int, rate_hz: float, *, ks=(8, 10, 12, 14, 16),
     return out
 
 
-def request_problem(req: dict, trotter_steps: int = 40) -> Problem:
+def request_problem(req: dict, trotter_steps: int = 40, dense_max_k: int = 12) -> Problem:
     """Circuit, gates and target of one serving request.  Targets are dense
-    exp(-iHt) for k <= 12 and a Strang Trotter gate list beyond."""
+    exp(-iHt) for k <= dense_max_k and a Strang Trotter gate list beyond."""
     rng = np.random.default_rng([SEED, 5, req["rid"] + 1])
     k = req["k"]
     pairs, layer_of = brickwall_pairs(k, req["depth"])
@@ -145,7 +145,7 @@ def request_problem(req: dict, trotter_steps: int = 40) -> Problem:
                    layer_of=np.asarray(layer_of, dtype=np.int32),
                    param_of=np.arange(len(pairs), dtype=np.int32), gates=gates,
                    direction=direction, parity=False, U=req["U"], t=req["t"])
-    if k <= 12:
+    if k <= dense_max_k:
         prob.U_ref = target_unitary(k // 2, req["t"], 1.0, req["U"])
     else:
         prob.trotter = strang_trotter_gates(k // 2, req["t"], trotter_steps, 1.0, req["U"])
