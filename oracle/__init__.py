@@ -32,6 +32,7 @@ from .dense import (  # noqa: F401
     euclidean_T,
     tangent_T,
     hessian_holomorphic,
+    hessian_by_holes,
     reference_columns,
     sector_columns,
 )

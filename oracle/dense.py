@@ -227,3 +227,51 @@ def hessian_holomorphic(k, pairs, gates, Ucols, cols=None, mask=None, inputs=Non
                 _, Td = tangent_T(k, pairs, gates, Zs, Ucols, cols, inputs)
                 H[:, :, :, l, a, b] = Td
     return H
+
+
+def hessian_by_holes(k, pairs, gates, Ucols, cols=None, mask=None, inputs=None) -> np.ndarray:
+    """The same second derivatives as hessian_holomorphic (N x 4 x 4 x N x 4 x 4),
+    computed by the steps of Sec. "Efficient gradient and Hessian
+    computation" and Sec. "Gate hole application": for every gate l, the
+    hole of G_l applied to the state before it gives one state per gate
+    entry (a, b) -- the embedded elementary matrix |a><b| acting on
+    psi_{l-1}; these states run through G_{l+1}, G_{l+2}, ... (the second
+    forward pass), and at every later gate m the hole of G_m is contracted
+    between the bra-side state after m and the propagated state before m,
+    which is d^2 h / dG_m[c,d] dG_l[a,b].  The other triangle follows by
+    symmetry of mixed derivatives; blocks with l == m vanish (h is linear in
+    each gate).  ``mask`` restricts both entries (a, b) and (c, d) to a
+    pattern (parity mode; the other entries are zero).  Memory: 16 propagated
+    states of the size of Ucols."""
+    N = len(pairs)
+    n = np.asarray(Ucols).shape[1]
+    Lam = backward_states(k, pairs, gates, Ucols)
+    H = np.zeros((N, 4, 4, N, 4, 4), dtype=np.complex128)
+    entries = [(a, b) for a in range(4) for b in range(4) if mask is None or mask[a, b]]
+    Psi = _initial(k, cols, inputs)
+    for l in range(N):
+        if l + 1 < N:
+            # hole application: one state per entry, stacked as columns
+            X = np.concatenate([apply_gate(Psi, k, pairs[l], _elementary(a, b))
+                                for a, b in entries], axis=1)
+            for m in range(l + 1, N):
+                qh, ql = pairs[m]
+                lam = np.moveaxis(Lam[m + 1].reshape([2] * k + [n]), [qh, ql], [0, 1])
+                xs = np.moveaxis(X.reshape([2] * k + [len(entries), n]), [qh, ql], [0, 1])
+                # block[c, d, e] = sum_{rest, j} Lam[(c, rest), j] X_e[(d, rest), j]
+                blk = np.tensordot(lam.reshape(4, -1, n), xs.reshape(4, -1, len(entries), n),
+                                   axes=([1, 2], [1, 3]))
+                if mask is not None:
+                    blk = np.where(mask[:, :, None], blk, 0)
+                for e, (a, b) in enumerate(entries):
+                    H[m, :, :, l, a, b] = blk[:, :, e]
+                    H[l, a, b, m, :, :] = blk[:, :, e]
+                X = apply_gate(X, k, pairs[m], gates[m])
+        Psi = apply_gate(Psi, k, pairs[l], gates[l])
+    return H
+
+
+def _elementary(a, b) -> np.ndarray:
+    E = np.zeros((4, 4), dtype=np.complex128)
+    E[a, b] = 1.0
+    return E

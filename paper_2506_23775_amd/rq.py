@@ -283,6 +283,12 @@ def _workspace(nbytes: int, stream, key=()) -> Workspace:
     return ws
 
 
+def release_workspaces():
+    """Drop the cached default workspaces (their memory returns to torch's
+    caching allocator once the work enqueued on their streams is done)."""
+    _ws_cache.clear()
+
+
 def default_chunk(circuit: Circuit, op: int, dtype: int, ncols: int,
                   budget_bytes: int = 24 << 30) -> int:
     """Largest power-of-two chunk (>= 64, <= padded column count) whose

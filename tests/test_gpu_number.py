@@ -13,7 +13,7 @@ from gpu_helpers import oracle_eval, rel
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: dict(f=1e-12, v=1e-10), 1: dict(f=1e-5, v=2e-5)}
+TOL = {0: dict(f=1e-12, v=1e-10), 1: dict(f=1e-5, v=1e-5)}
 NSEL = [0, 15, 5, 6, 9, 10]   # row-major positions of (0,0),(3,3),(1,1),(1,2),(2,1),(2,2)
 
 

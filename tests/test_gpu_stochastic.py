@@ -14,7 +14,7 @@ from gpu_helpers import rel, sector_full_index
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: dict(f=1e-12, v=1e-10), 1: dict(f=1e-5, v=2e-5)}
+TOL = {0: dict(f=1e-12, v=1e-10), 1: dict(f=1e-5, v=1e-5)}
 
 
 @pytest.fixture(scope="module")

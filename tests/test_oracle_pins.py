@@ -261,6 +261,37 @@ def test_hessian_holomorphic_blocks(rng):
         assert abs(H[l, a, b, m, c, d] - c11) < 1e-11
 
 
+def test_hessian_by_holes_equals_dual_numbers_and_taylor(rng):
+    """The hole-array Hessian (hole application, second forward pass,
+    contraction at every later gate) equals the dual-number Hessian
+    element by element (general and parity gates, full trace and a column
+    subset), and sampled entries equal bivariate Taylor coefficients of h."""
+    for k, layers, parity in [(6, 3, False), (4, 4, True), (6, 3, True)]:
+        pairs, gates = _random_circuit(rng, k, layers, parity)
+        U = _random_unitary(rng, 1 << k)
+        mask = O.riemann.PARITY_MASK if parity else None
+        for cols in (None, np.array([0, 3, 9, (1 << k) - 1])):
+            Uc = U if cols is None else U[:, cols]
+            A = O.hessian_holomorphic(k, pairs, gates, Uc, cols, mask=mask)
+            B = O.hessian_by_holes(k, pairs, gates, Uc, cols, mask=mask)
+            if mask is not None:
+                A = np.where(mask[None, :, :, None, None, None] & mask[None, None, None, None],
+                             A, 0)
+            assert np.abs(A - B).max() < 1e-13 * max(1.0, np.abs(A).max())
+    k = 4
+    pairs, gates = _random_circuit(rng, k, 3)
+    U = _random_unitary(rng, 1 << k)
+    H = O.hessian_by_holes(k, pairs, gates, U)
+    M, r = 4, 0.5
+    zz = r * np.exp(2j * np.pi * np.arange(M) / M)
+    for (l, a, b, m, c, d) in [(0, 3, 1, 4, 2, 0), (5, 1, 1, 2, 0, 3)]:
+        Xl = np.zeros_like(gates); Xl[l, a, b] = 1
+        Ym = np.zeros_like(gates); Ym[m, c, d] = 1
+        vals = np.array([[O.h_trace(k, pairs, gates + s * Xl + t * Ym, U) for t in zz] for s in zz])
+        c11 = np.fft.fft2(vals)[1, 1] / M ** 2 / r ** 2
+        assert abs(H[l, a, b, m, c, d] - c11) < 1e-11
+
+
 def _retract_cost(k, pairs, gates, U, X, eps):
     cand = np.stack([O.polar(gates[p] + eps * X[p]) for p in range(len(gates))])
     return O.cost(k, pairs, cand, U)
