@@ -63,7 +63,7 @@ EXPORTS = ["rq_workspace_bytes", "rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks
            "rq_hess_workspace_bytes", "rq_apply_circuit", "rq_tr_step", "rq_tr_accept",
            "rq_tangent_coords", "rq_tr_workspace_bytes", "rq_tr_solve",
            "rq_tangent_basis", "rq_plan_passes", "rq_profile_enable", "rq_profile_read",
-           "rq_stream_copy", "rq_strerror", "rq_last_error"]
+           "rq_stream_copy", "rq_hvp_static", "rq_strerror", "rq_last_error"]
 
 
 def lib():
@@ -103,11 +103,13 @@ def lib():
     L.rq_profile_enable.argtypes = [C.c_int]
     L.rq_profile_read.argtypes = [dp, C.POINTER(C.c_int64), dp, dp]
     L.rq_stream_copy.argtypes = [P, P, C.c_size_t, C.c_int32, C.c_int32, P]
+    L.rq_hvp_static.argtypes = common + [dp, C.POINTER(_Range), P, C.c_uint32,
+                                         C.POINTER(C.c_int64), P, P, P, P, P]
     L.rq_strerror.restype = C.c_char_p
     L.rq_last_error.restype = C.c_char_p
     for name in ["rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks", "rq_apply_circuit",
                  "rq_tr_step", "rq_tr_accept", "rq_tangent_basis", "rq_plan_passes",
-                 "rq_tangent_coords", "rq_tr_solve", "rq_stream_copy",
+                 "rq_tangent_coords", "rq_tr_solve", "rq_stream_copy", "rq_hvp_static",
                  "rq_profile_enable", "rq_profile_read"]:
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -400,6 +402,24 @@ def rq_hvp(circuit: Circuit, target: Target, gates, direction, range=None, chunk
     _check(lib().rq_hvp(C.byref(circuit._c), C.byref(t), _dptr(g), _dptr(d), _range(range),
                         C.byref(ex), _ptr(f), _ptr(eg), _ptr(rg), _ptr(eh), _ptr(rh)), "rq_hvp")
     return f[0], _cplx(eg), _cplx(rg), _cplx(eh), _cplx(rh)
+
+
+def rq_hvp_static(circuit: Circuit, target: Target, gates, direction, range=None, stream=None,
+                  out=None, accumulate=False):
+    """rq_hvp with the library's static scratch as workspace (no device
+    allocation inside the call).  Returns (f, egrad, rgrad, ehvp, rhvp,
+    chunk used).  Pass preallocated ``out`` tensors to allocate nothing."""
+    g = _gates_host(gates)
+    d = _gates_host(direction)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    f, eg, rg, eh, rh = _outputs(out, 5, circuit.n_params)
+    t = target.struct()
+    used = C.c_int64(0)
+    _check(lib().rq_hvp_static(C.byref(circuit._c), C.byref(t), _dptr(g), _dptr(d), _range(range),
+                               s.cuda_stream, RQ_EXEC_ACCUMULATE if accumulate else 0,
+                               C.byref(used), _ptr(f), _ptr(eg), _ptr(rg), _ptr(eh), _ptr(rh)),
+           "rq_hvp_static")
+    return f[0], _cplx(eg), _cplx(rg), _cplx(eh), _cplx(rh), used.value
 
 
 def rq_hess_blocks(circuit: Circuit, target: Target, gates, range=None, chunk=None,
