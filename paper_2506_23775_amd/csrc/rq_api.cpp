@@ -18,34 +18,19 @@ using namespace rqk;
 using cd = std::complex<double>;
 
 namespace rqk {
-struct HessArgs {
-  const void *coef;
-  void *psi;
-  const void *phi;
-  double *slots;
-  int64_t ld;
-  int64_t slab;
-  int32_t ncols, ncg, kq, n_items, nd, nslots, sector, ngates, ne;
-  uint32_t qmask;
-  int32_t pos[8];
-  GateRef gates[kMaxGates];
-};
 int launch_hess_pass(int is_double, int nt, int mode, const HessArgs &a, int grid, void *s);
-int launch_hole(int is_double, const void *src, void *dst, int64_t rows, int64_t ld, int ncols,
-                int nd, int k, int qh, int ql, int parity, int sector, void *s);
 int launch_copy_cols(int is_double, const void *src, int64_t ld_src, int64_t col0, void *dst,
                      int64_t rows, int64_t ld, int ncols, bool conj, void *s);
 int launch_onehot(int is_double, void *dst, int64_t rows, int64_t ld, int64_t col0, int ncols,
                   void *s);
 int launch_accum_rows(const double *slots, int rows, int nslots, double *acc, void *s);
+int launch_zero_cols(int is_double, void *p, int64_t n, int64_t rows, int64_t ld, int c0, int c1,
+                     void *s);
 int launch_hess_post(int N, int P, int structure, const double *hh, const int32_t *inst_off,
                      const int32_t *inst_list, const int32_t *ppos, const int32_t *map,
                      const double *gates64,
                      const double *egrad,
                      const double *basis, double *hess_holo, double *hess_real, void *s);
-// FP64 partial-sum slots (one per wavefront) of the Hessian sweeps: 3072
-// wavefronts, three per SIMD (a multiple of 4 x 6, 8 and 16 slices).
-constexpr int kHessSlots = 3072;
 }  // namespace rqk
 
 namespace {
@@ -687,12 +672,15 @@ int make_hess_layout(const rq_circuit *c, int32_t dtype, int64_t chunk, HessLayo
   H.P = c->n_params;
   H.nd = L.number ? 6 : L.parity ? 8 : 16;
   H.ne = L.parity ? 16 : 32;
-  H.nt = L.kq >= 4 ? 4 : 2;
+  // tile qubits of the Hessian sweeps: 5 for complex64 parity gates (the
+  // slice tile, its contraction partials and phi values read from LDS fit the
+  // registers without spills), 4 otherwise; 2 for tiny circuits
+  H.nt = (!L.is_double && L.parity && L.kq >= 5) ? 5 : L.kq >= 4 ? 4 : 2;
   H.esize = L.esize;
   H.rows = L.rows;
   H.chunk = chunk;
   H.slab_bytes = size_t(L.rows) * size_t(chunk) * L.esize;
-  if ((int64_t(1) << (L.kq - H.nt)) * ((chunk + 63) / 64) * H.nd >= (int64_t(1) << 31))
+  if ((int64_t(1) << (L.kq - H.nt)) * ((chunk + 63) / 64) >= (int64_t(1) << 31))
     return fail(RQ_EINVAL, "problem too large for one Hessian sweep grid (reduce chunk)");
   size_t o = L.total;
   H.off_coef = o;
@@ -947,7 +935,12 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
                         [&] { return launch_pass(L.is_double, 2, L.parity, OP_COST, ST_FWD, a, grid2, s); }))
           return fail(RQ_EHIP, "forward state launch failed");
       }
-      // phi at the output side of every gate along pi (slab = instance)
+      // phi at the output side of every gate along pi (slab = instance); the
+      // passes write valid columns only, and the Hessian sweep reads whole
+      // 64-column groups of phi: zero the padding of a ragged last group
+      if (ncols % 64 &&
+          launch_zero_cols(L.is_double, phi, N, H.rows, H.chunk, ncols, ncg * 64, s))
+        return fail(RQ_EHIP, "padding launch failed");
       if (launch_copy_cols(L.is_double, ref, t->ld, j0, slab(phi, order[N - 1]), H.rows, H.chunk,
                            ncols, true, s))
         return fail(RQ_EHIP, "target launch failed");
@@ -961,39 +954,40 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
           return fail(RQ_EHIP, "backward state launch failed");
       }
       // hole-array sweeps: hole at the t-th gate of pi, then the rest of its
-      // pass and every later pass
+      // pass and every later pass.  A block of four wavefronts takes four
+      // slices of one (tile, column group) item; ceil(nd / 4) blocks cover an
+      // item, and the grid strides over the items (one FP64 slot per
+      // wavefront, at most kHessSlots).
       ha.ncols = ncols;
       ha.ncg = ncg;
-      ha.n_items = (int)((int64_t(1) << (L.kq - H.nt)) * ncg * H.nd);
-      // a wavefront keeps one slice (mu = wave % nd) over all its items, so
-      // when it takes several items the wavefront count is a multiple of nd
-      // (and of the 4 wavefronts of a block)
-      const int unit = H.nd % 4 == 0 ? H.nd : 4 * H.nd / (H.nd % 2 == 0 ? 2 : 1);
-      const int waves = ha.n_items <= kHessSlots ? ha.n_items : kHessSlots / unit * unit;
-      const int gridh = (waves + 3) / 4;
+      ha.n_rest = (int)((int64_t(1) << (L.kq - H.nt)) * ncg);
+      ha.nquads = (H.nd + 3) / 4;
+      const int gridh =
+          ha.nquads * (int)std::min<int64_t>(ha.n_rest, kHessSlots / 4 / ha.nquads);
       const int rows_all = N * H.nd * H.ne;
       for (int t = 0; t + 1 < N; ++t) {
         const int h = order[t];
         if (!sweep[h]) continue;
-        const int qh = c->pairs[2 * h], ql = c->pairs[2 * h + 1];
-        if (prof_launch(s, 14, slab_amps * (1 + H.nd) * L.esize, 0.0, [&] {
-              return launch_hole(L.is_double, slab(psi, t), arr, H.rows, H.chunk, ncols, H.nd,
-                                 c->n_qubits, qh, ql, L.parity ? (L.number ? 2 : 1) : 0,
-                                 sector, s);
-            }))
-          return fail(RQ_EHIP, "hole launch failed");
         if (launch_zero(slots, int64_t(rows_all) * kHessSlots, s))
           return fail(RQ_EHIP, "zero launch failed");
         for (size_t i = pass_of[h]; i < full.size(); ++i) {
           const PlanPass &pp = full[i];
-          const size_t j0g = i == (size_t)pass_of[h] ? size_t(pos_in[h]) + 1 : 0;
-          if (j0g >= pp.gates.size()) continue;
+          // the first pass starts at the hole gate itself: its slices are
+          // built from psi before it, then the rest of the pass follows
+          const bool first = i == (size_t)pass_of[h];
+          const size_t j0g = first ? size_t(pos_in[h]) : 0;
+          const int ncontract = (int)(pp.gates.size() - j0g) - (first ? 1 : 0);
+          ha.hole_src = first ? slab(psi, t) : nullptr;
           ha.qmask = pp.qmask;
           for (int b = 0; b < 8; ++b) ha.pos[b] = pp.pos[b];
           ha.ngates = (int)(pp.gates.size() - j0g);
           for (int g = 0; g < ha.ngates; ++g) ha.gates[g] = pp.gates[j0g + g];
-          if (prof_launch(s, 12, slab_amps * (2 * H.nd + ha.ngates) * L.esize,
-                          slab_amps * H.nd * ha.ngates * (L.parity ? 32 : 64),
+          // algorithmic bytes: slices written (and read, after the first
+          // pass), psi read once in the first pass, phi of every contracted
+          // gate read once
+          const double slabs = first ? H.nd + 1 + ncontract : 2 * H.nd + ncontract;
+          if (prof_launch(s, 12, slab_amps * slabs * L.esize,
+                          slab_amps * H.nd * ncontract * (L.parity ? 32 : 64),
                           [&] { return launch_hess_pass(L.is_double, H.nt, L.parity, ha, gridh, s); }))
             return fail(RQ_EHIP, "Hessian pass launch failed");
         }

@@ -8,34 +8,27 @@
 //   - at every later gate m the hole of G_m is sandwiched between phi at the
 //     output side of m and the array at its input side, giving the block
 //     d^2 h / dG_l[a,b] dG_m[a',b'].
-// GPU design: the slices are independent slabs; a wavefront owns one slice
-// and 64 basis columns, keeps the 2^NT amplitudes of its tile in registers,
-// and fuses every gate of a sweep pass (contraction, then application).  The
-// phi states at each gate output come from a stored per-gate backward sweep
-// and are shared by the slices (read through the L2).  Contractions use the
-// same FP64 wavefront reduce-scatter and per-wave slots as the gradient.
+// GPU design: a block of four wavefronts owns four slices of one (tile,
+// 64-column group) item at a time; each wavefront keeps the 2^NT amplitudes
+// of its slice on the tile in registers and fuses every gate of a sweep pass
+// (contraction, then application).  The phi tile at each gate output (from
+// a stored per-gate backward sweep) is brought into LDS once per block by
+// direct global->LDS loads, double-buffered one gate ahead, and read by the
+// four slices, so phi crosses HBM once per item instead of once per slice.
+// In the first pass after the hole the slices are built in registers from
+// the tile of psi before the hole gate (no separate hole-array pass).
+// Contractions use the FP64 wavefront reduce-scatter and per-wave slots of
+// the gradient.
 #include "rq_sweep.h"
 
 #define CV(x) decltype(x)::value
 
 namespace rqk {
 
-struct HessArgs {
-  const void *coef;
-  void *psi;           // hole-array slices [nd][rows][ld]
-  const void *phi;     // phi at the output side of every gate [N][rows][ld]
-  double *slots;       // [((m * nd + mu) * ne + e) * nslots + wave]
-  int64_t ld;
-  int64_t slab;        // rows * ld (elements)
-  int32_t ncols, ncg, kq, n_items, nd, nslots, sector, ngates, ne;
-  uint32_t qmask;
-  int32_t pos[8];
-  GateRef gates[kMaxGates];
-};
-
-// tp[(a', b')] += phi[a'] psi[b'] over the groups of the gate's qubits.
+// tp[(a', b')] += phi[a'] psi[b'] over the groups of the gate's qubits, phi
+// read from the LDS tile ph (amplitude i of this lane at ph[i * 64]).
 template <typename R, int NT, int MODE, int C, int NE, int NA>
-__device__ __forceinline__ void contract_gate(const cx<R> (&ps)[NA], const cx<R> (&ph)[NA],
+__device__ __forceinline__ void contract_gate(const cx<R> (&ps)[NA], const cx<R> *ph,
                                               R (&tp)[NE]) {
   using K = Codes<MODE, NT>;
   if constexpr (K::template valid<C>()) {
@@ -43,9 +36,11 @@ __device__ __forceinline__ void contract_gate(const cx<R> (&ps)[NA], const cx<R>
     if constexpr (MODE == MODE_DENSE) {
       for_groups<NT, H, L>([&](auto I0, auto I1, auto I2, auto I3) __attribute__((always_inline)) {
         constexpr int id[4] = {CV(I0), CV(I1), CV(I2), CV(I3)};
+        cx<R> p[4];
+        static_for<0, 4>([&](auto A) __attribute__((always_inline)) { p[CV(A)] = ph[id[CV(A)] * 64]; });
         static_for<0, 16>([&](auto AB) __attribute__((always_inline)) {
           constexpr int a = CV(AB) / 4, b = CV(AB) % 4, e = 2 * CV(AB);
-          cacc(tp[e], tp[e + 1], ph[id[a]], ps[id[b]]);
+          cacc(tp[e], tp[e + 1], p[a], ps[id[b]]);
         });
       });
     } else {
@@ -53,12 +48,86 @@ __device__ __forceinline__ void contract_gate(const cx<R> (&ps)[NA], const cx<R>
       for_blocks<NT, KD, H, L, PI>([&](auto J0, auto J1, auto C00, auto C01, auto C10,
                                        auto C11) __attribute__((always_inline)) {
         constexpr int i0 = CV(J0), i1 = CV(J1);
-        cacc(tp[2 * CV(C00)], tp[2 * CV(C00) + 1], ph[i0], ps[i0]);
-        cacc(tp[2 * CV(C01)], tp[2 * CV(C01) + 1], ph[i0], ps[i1]);
-        cacc(tp[2 * CV(C10)], tp[2 * CV(C10) + 1], ph[i1], ps[i0]);
-        cacc(tp[2 * CV(C11)], tp[2 * CV(C11) + 1], ph[i1], ps[i1]);
+        const cx<R> p0 = ph[i0 * 64], p1 = ph[i1 * 64];
+        cacc(tp[2 * CV(C00)], tp[2 * CV(C00) + 1], p0, ps[i0]);
+        cacc(tp[2 * CV(C01)], tp[2 * CV(C01) + 1], p0, ps[i1]);
+        cacc(tp[2 * CV(C10)], tp[2 * CV(C10) + 1], p1, ps[i0]);
+        cacc(tp[2 * CV(C11)], tp[2 * CV(C11) + 1], p1, ps[i1]);
       });
     }
+  }
+}
+
+// Gate-hole application on a register tile: slice (a, b) of the array is the
+// state with the gate's pair bits moved from b to a, zero where the pair bits
+// of the amplitude differ from a.  ps holds the state before the hole gate on
+// entry and the slice on exit.  Pair value of local amplitude i: both bits
+// local (kind 0), or one of them the implied qubit k-1 whose bit is
+// PI ^ parity(i) (kinds 1, 2; see for_blocks).
+template <typename R, int NT, int MODE, int C, int NA>
+__device__ __forceinline__ void hole_slice(cx<R> (&ps)[NA], int a, int b) {
+  using K = Codes<MODE, NT>;
+  if constexpr (K::template valid<C>()) {
+    constexpr int H = K::template h<C>(), L = K::template l<C>();
+    constexpr int KD = MODE == MODE_DENSE ? 0 : K::template kind<C>();
+    constexpr int PI = MODE == MODE_DENSE ? 0 : K::template pi<C>();
+    // (component-wise selects: a select of whole structs becomes an indexed
+    // stack access)
+    auto put = [&](cx<R> &dst, bool keep, R x, R y) __attribute__((always_inline)) {
+      dst.x = keep ? x : R(0);
+      dst.y = keep ? y : R(0);
+    };
+    if constexpr (KD == 0) {
+      // groups of four amplitudes with pair values 0..3
+      for_groups<NT, H, L>([&](auto I0, auto I1, auto I2, auto I3) __attribute__((always_inline)) {
+        constexpr int id[4] = {CV(I0), CV(I1), CV(I2), CV(I3)};
+        R vx = b == 1 ? ps[id[1]].x : ps[id[0]].x, vy = b == 1 ? ps[id[1]].y : ps[id[0]].y;
+        vx = b == 2 ? ps[id[2]].x : vx;
+        vy = b == 2 ? ps[id[2]].y : vy;
+        vx = b == 3 ? ps[id[3]].x : vx;
+        vy = b == 3 ? ps[id[3]].y : vy;
+        static_for<0, 4>([&](auto J) __attribute__((always_inline)) {
+          put(ps[id[CV(J)]], a == CV(J), vx, vy);
+        });
+      });
+    } else {
+      // pairs differing in the explicit bit H; the implied bit is
+      // PI ^ parity(local index)
+      static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+        constexpr int i0 = CV(I);
+        if constexpr (!((i0 >> H) & 1)) {
+          constexpr int i1 = i0 | (1 << H);
+          constexpr int be0 = PI ^ (__builtin_popcount(i0) & 1), be1 = be0 ^ 1;
+          constexpr int pv0 = KD == 1 ? be0 : 2 * be0;
+          constexpr int pv1 = KD == 1 ? 2 + be1 : 2 * be1 + 1;
+          const R s0x = ps[i0].x, s0y = ps[i0].y, s1x = ps[i1].x, s1y = ps[i1].y;
+          const R vx = b == pv0 ? s0x : (b == pv1 ? s1x : R(0));
+          const R vy = b == pv0 ? s0y : (b == pv1 ? s1y : R(0));
+          ps[i0].x = a == pv0 ? vx : R(0);
+          ps[i0].y = a == pv0 ? vy : R(0);
+          ps[i1].x = a == pv1 ? vx : R(0);
+          ps[i1].y = a == pv1 ? vy : R(0);
+        }
+      });
+    }
+  }
+}
+
+// Slice mu -> gate entry (a, b): dense 4x4 row-major; parity pattern
+// (0,0),(0,3),(3,0),(3,3),(1,1),(1,2),(2,1),(2,2); particle number the same
+// without (0,3), (3,0).
+__device__ __forceinline__ void slice_entry(int mode, int nd, int mu, int &a, int &b) {
+  if (mode == MODE_DENSE) {
+    a = mu >> 2;
+    b = mu & 3;
+  } else if (nd == 6) {
+    const int pa = 0x221130, pb = 0x212130;   // nibbles, entry 0 lowest
+    a = (pa >> (4 * mu)) & 0xF;
+    b = (pb >> (4 * mu)) & 0xF;
+  } else {
+    const int pa = 0x22113300, pb = 0x21213030;
+    a = (pa >> (4 * mu)) & 0xF;
+    b = (pb >> (4 * mu)) & 0xF;
   }
 }
 
@@ -68,15 +137,31 @@ __global__ __launch_bounds__(kBlock) void k_hess_pass(const HessArgs A) {
   constexpr int NE = MODE == MODE_DENSE ? 32 : 16;
   constexpr int LV = ilog2<NE>();
   constexpr uint32_t ES = sizeof(cx<R>);
+  constexpr int DW = int(ES) / 4;
+  // phi rows loaded by each of the four wavefronts per gate; one direct load
+  // moves 16 bytes per lane: two rows of 64 complex64 columns (lanes 0-31 /
+  // 32-63), or one row of complex128
+  constexpr int ROWS_PER_LOAD = DW == 2 ? 2 : 1;
+  constexpr int TOTAL_LOADS = NA / ROWS_PER_LOAD;        // per tile, over the block
+  constexpr int LOADS = (TOTAL_LOADS + 3) / 4;           // per wavefront (at most)
   using K = Codes<MODE, NT>;
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
   const int gwave = blockIdx.x * (kBlock / 64) + wib;
-  const int nwaves = gridDim.x * (kBlock / 64);
-  double *acc = lds + wib * (kMaxGates * NE);
+  cx<R> *phb = reinterpret_cast<cx<R> *>(lds);                       // [2][NA][64]
+  double *acc = reinterpret_cast<double *>(phb + 2 * NA * 64) + wib * (kMaxGates * NE);
   const int my_e = entry_of_lane(lane, LV);
   const bool writer = entry_writer(lane, LV);
+  // block -> (slice quad, first item); the four wavefronts of a block take
+  // four consecutive slices of the same items
+  const int quad = blockIdx.x % A.nquads;
+  const int rest0 = blockIdx.x / A.nquads;
+  const int rstride = gridDim.x / A.nquads;
+  const int mu = quad * 4 + wib;
+  const bool active = mu < A.nd;           // particle-number mode pads 6 slices to 8
+  int ea = 0, eb = 0;
+  slice_entry(MODE, A.nd, active ? mu : 0, ea, eb);
   for (int g = 0; g < A.ngates; ++g)
     if (writer) acc[g * NE + my_e] = 0.0;
   ccoef_t<R> *coef = as_const_coef<R>(A.coef);
@@ -91,41 +176,84 @@ __global__ __launch_bounds__(kBlock) void k_hess_pass(const HessArgs A) {
     });
     return o;
   };
-  const int mu = gwave % A.nd;  // every item of this wavefront has the same slice
-  for (int item = gwave; item < A.n_items; item += nwaves) {
-    const int rest = item / A.nd;
+  auto tile_base = [&](int rest) {
+    int t = rest / A.ncg;
+    int64_t base = 0;
+    for (int p = 0; p < A.kq; ++p)
+      if (!((A.qmask >> p) & 1)) {
+        base |= int64_t(t & 1) << p;
+        t >>= 1;
+      }
+    return base;
+  };
+  const int g0 = A.hole_src ? 1 : 0;       // first gate with a contraction
+  const bool any_phi = A.ngates > g0;
+  // direct loads of this wavefront's rows of the phi tile of gate g, item rest
+  auto prefetch = [&](int rest, int g, int buf) __attribute__((always_inline)) {
     const int cg = rest % A.ncg;
-    const int tile = rest / A.ncg;
+    const int64_t rowb = tile_base(rest) * A.ld * ES;
+    const char *src = reinterpret_cast<const char *>(A.phi) +
+                      int64_t(A.gates[g].inst) * A.slab * ES + rowb + int64_t(cg) * 64 * ES;
+    static_for<0, LOADS>([&](auto Q) __attribute__((always_inline)) {
+      const int li = CV(Q) * 4 + wib;        // load index of this wavefront
+      if (TOTAL_LOADS % 4 == 0 || li < TOTAL_LOADS) {
+        const int r0 = li * ROWS_PER_LOAD;
+        // byte offset of local row r (runtime: wib varies over the block)
+        int64_t ro = 0;
+        const int r = DW == 2 ? r0 + (lane >> 5) : r0;
+        static_for<0, NT>([&](auto B) __attribute__((always_inline)) {
+          if ((r >> CV(B)) & 1) ro += bstep[CV(B)];
+        });
+        const uint32_t coff = DW == 2 ? uint32_t(lane & 31) * 16 : uint32_t(lane) * 16;
+        lds_dma<16>(src + ro + coff, phb + (buf * NA + r0) * 64);
+      }
+    });
+  };
+
+  int buf = 0;
+  if (any_phi && rest0 < A.n_rest) prefetch(rest0, g0, 0);
+  for (int rest = rest0; rest < A.n_rest; rest += rstride) {
+    const int cg = rest % A.ncg;
     const int c = cg * 64 + lane;
     const bool ok = c < A.ncols;
     const int cc = ok ? c : A.ncols - 1;
     const uint32_t voff = uint32_t(cc) * ES;
-    int64_t base = 0;
-    {
-      int t = tile;
-      for (int p = 0; p < A.kq; ++p)
-        if (!((A.qmask >> p) & 1)) {
-          base |= int64_t(t & 1) << p;
-          t >>= 1;
-        }
-    }
+    const int64_t base = tile_base(rest);
     const int pi = MODE == MODE_PARITY ? ((A.sector ^ __builtin_popcountll(base)) & 1) : 0;
     const int64_t rowb = base * A.ld * ES;
     const cx<R> zero{R(0), R(0)};
-    char *sl = reinterpret_cast<char *>(A.psi) + int64_t(mu) * A.slab * ES + rowb;
-    cx<R> ps[NA], ph[NA];
+    char *sl = reinterpret_cast<char *>(A.psi) + int64_t(active ? mu : 0) * A.slab * ES + rowb;
+    const char *ld_src = A.hole_src ? reinterpret_cast<const char *>(A.hole_src) + rowb : sl;
+    cx<R> ps[NA];
     static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
-      const cx<R> v = ldrow<R>(sl + boff(I), voff);
+      const cx<R> v = ldrow<R>(ld_src + boff(I), voff);
       ps[CV(I)] = ok ? v : zero;
     });
-    for (int g = 0; g < A.ngates; ++g) {
+    if (A.hole_src) {
+      const GateRef gr = A.gates[0];
+      dispatch<0, K::n>(gate_code(MODE, NT, gr, pi), [&](auto CC) __attribute__((always_inline)) {
+        hole_slice<R, NT, MODE, CV(CC)>(ps, ea, eb);
+      });
+    }
+    for (int g = g0; g < A.ngates; ++g) {
+      // this gate's phi tile is in LDS buffer `buf` once every wavefront's
+      // loads completed: only this item's slice loads (NA vector-memory
+      // instructions) were issued after it in the first gate, none later
+      if (g == g0)
+        wait_vmcnt<NA>();
+      else
+        wait_vmcnt<0>();
+      __syncthreads();
+      // the other buffer was last read for the previous gate, which every
+      // wavefront finished before the barrier: prefetch the next gate into it
+      if (g + 1 < A.ngates)
+        prefetch(rest, g + 1, buf ^ 1);
+      else if (rest + rstride < A.n_rest)
+        prefetch(rest + rstride, g0, buf ^ 1);
+      asm volatile("" ::: "memory");
       const GateRef gr = A.gates[g];
       ccoef_t<R> *co = coef + int64_t(gr.inst) * kCoefStride;
-      const char *pp = reinterpret_cast<const char *>(A.phi) + int64_t(gr.inst) * A.slab * ES + rowb;
-      static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
-        const cx<R> v = ldrow<R>(pp + boff(I), voff);
-        ph[CV(I)] = ok ? v : zero;
-      });
+      const cx<R> *ph = phb + buf * NA * 64 + lane;
       R tp[NE];
       // -0: the first fma into each partial folds into a multiply
       static_for<0, NE>([&](auto E) __attribute__((always_inline)) { tp[CV(E)] = R(-0.0); });
@@ -135,57 +263,21 @@ __global__ __launch_bounds__(kBlock) void k_hess_pass(const HessArgs A) {
       });
       const double r = wave_reduce_scatter<R, NE>(tp, lane);
       if (writer) acc[g * NE + my_e] += r;
+      buf ^= 1;
     }
-    if (ok)
+    if (ok && active) {
+      char *dst = reinterpret_cast<char *>(A.psi) + int64_t(mu) * A.slab * ES + rowb;
       static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
-        strow<R>(sl + boff(I), voff, ps[CV(I)]);
+        strow<R>(dst + boff(I), voff, ps[CV(I)]);
       });
+    }
   }
-  if (writer)
-    for (int g = 0; g < A.ngates; ++g) {
+  wait_vmcnt<0>();     // no direct load may still target LDS at exit
+  if (writer && active)
+    for (int g = g0; g < A.ngates; ++g) {
       double *s = A.slots + ((int64_t(A.gates[g].inst) * A.nd + mu) * A.ne + my_e) * A.nslots + gwave;
       *s += acc[g * NE + my_e];
     }
-}
-
-// Hole application: slice mu = (a, b) of the array is psi with the pair bits
-// of the hole gate moved from b to a (zero where the pair bits differ from a).
-template <typename R>
-__global__ void k_hole(const cx<R> *__restrict__ src, cx<R> *__restrict__ dst, int64_t rows,
-                       int64_t ld, int ncols, int nd, int k, int qh, int ql, int parity,
-                       int sector) {
-  const int64_t total = int64_t(nd) * rows * ld;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t c = i % ld;
-    const int64_t x = (i / ld) % rows;
-    const int mu = int(i / (ld * rows));
-    int a, b;
-    if (parity == 2) {  // particle number: (0,0),(3,3),(1,1),(1,2),(2,1),(2,2)
-      const int pa[6] = {0, 3, 1, 1, 2, 2}, pb[6] = {0, 3, 1, 2, 1, 2};
-      a = pa[mu];
-      b = pb[mu];
-    } else if (parity) {
-      const int pa[8] = {0, 0, 3, 3, 1, 1, 2, 2}, pb[8] = {0, 3, 0, 3, 1, 2, 1, 2};
-      a = pa[mu];
-      b = pb[mu];
-    } else {
-      a = mu >> 2;
-      b = mu & 3;
-    }
-    int64_t xf = x;
-    if (parity) xf = (x << 1) | ((__builtin_popcountll(x) & 1) ^ sector);
-    const int sh = k - 1 - qh, sl = k - 1 - ql;
-    const int bits = int(((xf >> sh) & 1) << 1 | ((xf >> sl) & 1));
-    cx<R> v{R(0), R(0)};
-    if (bits == a && c < ncols) {
-      int64_t sf = xf & ~((int64_t(1) << sh) | (int64_t(1) << sl));
-      sf |= (int64_t(b >> 1) << sh) | (int64_t(b & 1) << sl);
-      const int64_t sr = parity ? (sf >> 1) : sf;
-      v = src[sr * ld + c];
-    }
-    dst[i] = v;
-  }
 }
 
 // Columns col0..col0+ncols of a slab (row stride ld_src) into a chunk slab,
@@ -205,6 +297,21 @@ __global__ void k_copy_cols(const cx<R> *__restrict__ src, int64_t ld_src, int64
       if (conj) v.y = -v.y;
     }
     dst[i] = v;
+  }
+}
+
+// Zero columns [c0, c1) of n consecutive slabs of rows x ld elements: the
+// padding columns of a ragged chunk's last 64-column group, which the sweep
+// passes never write but the Hessian sweep reads (through LDS, unmasked).
+template <typename R>
+__global__ void k_zero_cols(cx<R> *__restrict__ p, int64_t n, int64_t rows, int64_t ld, int c0,
+                            int c1) {
+  const int w = c1 - c0;
+  const int64_t total = n * rows * w;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = i / w;                   // slab * rows + row
+    p[r * ld + c0 + (i % w)] = cx<R>{R(0), R(0)};
   }
 }
 
@@ -387,7 +494,9 @@ __global__ __launch_bounds__(256) void k_hess_post(
 template <typename R, int NT, int MODE>
 static int launch_hess_one(const HessArgs &a, int grid, void *s) {
   constexpr int NE = MODE == MODE_DENSE ? 32 : 16;
-  const size_t lds = size_t(kBlock / 64) * kMaxGates * NE * sizeof(double);
+  // phi double buffer [2][2^NT][64] and the wavefronts' FP64 accumulators
+  const size_t lds = size_t(2) * (1 << NT) * 64 * sizeof(cx<R>) +
+                     size_t(kBlock / 64) * kMaxGates * NE * sizeof(double);
   hipLaunchKernelGGL((k_hess_pass<R, NT, MODE>), dim3(grid), dim3(kBlock), lds, (hipStream_t)s,
                      a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -395,6 +504,7 @@ static int launch_hess_one(const HessArgs &a, int grid, void *s) {
 
 int launch_hess_pass(int is_double, int nt, int mode, const HessArgs &a, int grid, void *s) {
   if (!is_double) {
+    if (nt == 5 && mode) return launch_hess_one<float, 5, 1>(a, grid, s);
     if (nt == 4) return mode ? launch_hess_one<float, 4, 1>(a, grid, s) : launch_hess_one<float, 4, 0>(a, grid, s);
     if (nt == 2) return mode ? launch_hess_one<float, 2, 1>(a, grid, s) : launch_hess_one<float, 2, 0>(a, grid, s);
   } else {
@@ -407,20 +517,6 @@ int launch_hess_pass(int is_double, int nt, int mode, const HessArgs &a, int gri
 static int grid_of(int64_t total) {
   int64_t b = (total + 255) / 256;
   return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
-}
-
-int launch_hole(int is_double, const void *src, void *dst, int64_t rows, int64_t ld, int ncols,
-                int nd, int k, int qh, int ql, int parity, int sector, void *s) {
-  const int g = grid_of(int64_t(nd) * rows * ld);
-  if (is_double)
-    hipLaunchKernelGGL(k_hole<double>, dim3(g), dim3(256), 0, (hipStream_t)s,
-                       (const cx<double> *)src, (cx<double> *)dst, rows, ld, ncols, nd, k, qh, ql,
-                       parity, sector);
-  else
-    hipLaunchKernelGGL(k_hole<float>, dim3(g), dim3(256), 0, (hipStream_t)s,
-                       (const cx<float> *)src, (cx<float> *)dst, rows, ld, ncols, nd, k, qh, ql,
-                       parity, sector);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_copy_cols(int is_double, const void *src, int64_t ld_src, int64_t col0, void *dst,
@@ -446,6 +542,19 @@ int launch_onehot(int is_double, void *dst, int64_t rows, int64_t ld, int64_t co
   else
     hipLaunchKernelGGL(k_onehot<float>, dim3(g), dim3(256), 0, (hipStream_t)s, (cx<float> *)dst,
                        rows, ld, col0, ncols);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_zero_cols(int is_double, void *p, int64_t n, int64_t rows, int64_t ld, int c0, int c1,
+                     void *s) {
+  if (c1 <= c0 || n == 0) return 0;
+  const int g = grid_of(n * rows * (c1 - c0));
+  if (is_double)
+    hipLaunchKernelGGL(k_zero_cols<double>, dim3(g), dim3(256), 0, (hipStream_t)s,
+                       (cx<double> *)p, n, rows, ld, c0, c1);
+  else
+    hipLaunchKernelGGL(k_zero_cols<float>, dim3(g), dim3(256), 0, (hipStream_t)s,
+                       (cx<float> *)p, n, rows, ld, c0, c1);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -64,7 +64,32 @@ struct PassArgs {
   GateRef gates[kMaxGates];
 };
 
-// Host-side launchers (defined in rq_launch.hip and the sweep
+// One Hessian hole-array sweep pass (k_hess_pass): the nd slices of the
+// array of one hole gate through the gates of one pass, contracted against
+// the stored phi after each gate.
+struct HessArgs {
+  const void *coef;      // per-instance coefficients (state precision)
+  void *psi;             // hole-array slices [nd][rows][ld]
+  const void *phi;       // phi at the output side of every gate [N][rows][ld]
+  const void *hole_src;  // first pass after a hole: psi before the hole gate,
+                         // which is gate 0 of the list (no contraction there);
+                         // NULL: the slices are read from psi
+  double *slots;         // FP64 partials [((inst * nd + mu) * ne + e) * nslots + wave]
+  int64_t ld;            // row stride of the slabs (elements)
+  int64_t slab;          // rows * ld (elements)
+  int32_t ncols, ncg, kq;
+  int32_t n_rest;        // tiles * column groups
+  int32_t nd;            // slices (16 dense, 8 parity, 6 particle number)
+  int32_t nquads;        // blocks per item: ceil(nd / 4)
+  int32_t nslots, sector, ngates, ne;
+  uint32_t qmask;
+  int32_t pos[8];
+  GateRef gates[kMaxGates];
+};
+// FP64 partial-sum slots (one per wavefront) of the Hessian sweeps.
+constexpr int kHessSlots = 3072;
+
+// Host-side launchers (defined in rq_launch.hip, rq_hess.hip and the sweep
 // instantiation units).
 int launch_pass(int is_double, int nt, int mode, int op, int stage,
                 const PassArgs &a, int grid, void *stream);

@@ -234,3 +234,129 @@ def test_hessian_times_direction_equals_hvp_k16(rq, dtype):
     hx = O.gradient_real(prob.gates, _np(rh))
     assert rel(hr @ x, hx) <= TOL[dtype]["v"] * 10, rel(hr @ x, hx)
     assert np.abs(hr - hr.T).max() <= TOL[dtype]["v"] * 100 * np.abs(hr).max()
+
+
+# ---------------------------------------------------------------------------
+# Hessians at size: configuration 2 (all 4096 basis states, stored oracle
+# blocks), configuration 3 in the benchmark's launch configuration (shift 4,
+# whole sectors, chunk 1024), configuration 4 on ranges spanning 2^16
+# ---------------------------------------------------------------------------
+
+GOLDEN_H = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "config2_hessian.npz")
+HESS_TOL = {0: 1e-10, 1: 2e-5}
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_config2_hessian_golden(rq, dtype):
+    """All 30 x 30 instance blocks (480 x 480 real Riemannian Hessian) over
+    the full trace against the oracle's hole-array Hessian stored by
+    ``tests/golden/make_config2_hessian.py``."""
+    g = np.load(GOLDEN_H)
+    prob = w.make_problem(2)
+    N = len(prob.pairs)
+    circ = rq.Circuit(prob.k, prob.pairs, param_of=prob.param_of)
+    tgt = rq.Target.from_dense(prob.U_ref, dtype)
+    f, eg, _, hh, hr = rq.rq_hess_blocks(circ, tgt, prob.gates)
+    tol = HESS_TOL[dtype]
+    assert abs(float(f) - float(g["f"])) <= TOL[dtype]["f"] * max(1.0, abs(float(g["f"])))
+    assert rel(_np(eg), g["egrad"]) <= TOL[dtype]["v"]
+    iu = np.triu_indices(N, 1)
+    hh = _np(hh)                      # [P, 16, P, 16] (identity param_of)
+    assert rel(hh[iu[0], :, iu[1], :], g["holo_upper"]) <= tol
+    # lower blocks are the transposes, diagonal blocks vanish
+    assert rel(np.swapaxes(hh[iu[1], :, iu[0], :], 1, 2), g["holo_upper"]) <= tol
+    assert np.abs(hh[np.arange(N), :, np.arange(N), :]).max() <= tol * np.abs(hh).max()
+    Hr = np.zeros((16 * N, 16 * N))
+    Hr[np.triu_indices(16 * N)] = g["real_upper"]
+    Hr = Hr + np.triu(Hr, 1).T
+    assert rel(_np(hr), Hr) <= tol
+
+
+@pytest.mark.timeout(900)
+def test_config3_hessian_bench_launch_shift_equals_full_holes(rq):
+    """Configuration 3 (Strang target, two-site translation symmetry) at
+    k = 16 over both parity sectors in the benchmark's launch configuration
+    (shift 4, chunk 1024): translation-unique hole pairs equal the full hole
+    set in complex128 to 1e-12, and the benchmark's complex64 run equals
+    complex128 within the FP32-state tolerance."""
+    import torch
+    prob = w.make_problem(3, trotter_steps=20)
+    tgt = rq.build_trotter_target(prob.k, prob.trotter, dtype=rq.RQ_C128, parity=True)
+    c_shift = rq.Circuit(prob.k, prob.pairs, param_of=prob.param_of, parity=True, shift=4)
+    c_full = rq.Circuit(prob.k, prob.pairs, param_of=prob.param_of, parity=True)
+    res_s = [_np(x) for x in rq.rq_hess_blocks(c_shift, tgt, prob.gates, chunk=1024)]
+    _free()
+    res_f = [_np(x) for x in rq.rq_hess_blocks(c_full, tgt, prob.gates, chunk=1024)]
+    _free()
+    assert abs(float(res_s[0]) - float(res_f[0])) <= 1e-12 * max(1.0, abs(float(res_f[0])))
+    assert rel(res_s[3], res_f[3]) <= 1e-12, rel(res_s[3], res_f[3])
+    assert rel(res_s[4], res_f[4]) <= 1e-12, rel(res_s[4], res_f[4])
+    t64 = rq.Target(tgt.ref.to(torch.complex64), rq.RQ_C64, True)
+    del tgt
+    _free()
+    res_64 = [_np(x) for x in rq.rq_hess_blocks(c_shift, t64, prob.gates, chunk=1024)]
+    assert rel(res_64[3], res_f[3]) <= HESS_TOL[1], rel(res_64[3], res_f[3])
+    assert rel(res_64[4], res_f[4]) <= HESS_TOL[1], rel(res_64[4], res_f[4])
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_config3_hessian_full_trace_sparse_target_vs_oracle(rq, dtype):
+    """The full hole set (no shift) over the full trace of both sectors at
+    chunk 1024, with a target that is zero except on sampled columns of both
+    sectors (first / last columns, both sides of a chunk edge): sampled
+    Hessian columns equal the oracle's directional derivatives of T summed
+    over the sampled basis states."""
+    prob = w.make_problem(3)
+    k = prob.k
+    n = 1 << (k - 1)
+    picks = [(0, 0), (0, 1023), (0, 1024), (1, 20000), (1, n - 1)]
+    rng = np.random.default_rng([w.configs.SEED, 3, 104])
+    tgt, full, cols = sparse_target(rq, k, True, dtype, picks, rng)
+    circ = rq.Circuit(k, prob.pairs, param_of=prob.param_of, parity=True)
+    _, _, _, hh, _ = rq.rq_hess_blocks(circ, tgt, prob.gates, chunk=1024)
+    hh = _np(hh)
+    for (p, a, b) in [(0, 0, 0), (3, 1, 2), (6, 3, 3), (5, 0, 3), (2, 2, 1)]:
+        ec = PIDX.index(4 * a + b)
+        col = _oracle_hessian_column(k, prob.pairs, prob.gates, prob.param_of, full, cols,
+                                     p, a, b, True)
+        got = hh[:, :, p, ec].reshape(-1, 8)
+        assert rel(got, col) <= HESS_TOL[dtype], (p, a, b, rel(got, col))
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_config4_hessian_ranges_vs_oracle_and_tr_step(rq, dtype):
+    """Configuration 4 (72 independent gates, k = 16): Hessian blocks over
+    basis ranges at the start, across a chunk edge in the middle and at the
+    end of the 2^16 columns, each against the oracle's Hessian columns on the
+    sampled states; the trust-region step on the device Hessian and gradient
+    against the oracle's step on the same inputs."""
+    prob = w.make_problem(4)
+    k = prob.k
+    rng = np.random.default_rng([w.configs.SEED, 4, 105])
+    circ = rq.Circuit(k, prob.pairs, param_of=prob.param_of)
+    for j0, width, chunk, picked in [(0, 64, 64, (0, 63)),
+                                     (2048 - 64, 128, 64, (1984, 2047, 2048, 2111)),
+                                     ((1 << k) - 64, 64, 64, ((1 << k) - 2, (1 << k) - 1))]:
+        tgt, full, cols = sparse_target(rq, k, False, dtype, [(-1, j) for j in picked], rng,
+                                        window=(j0, width))
+        f, eg, _, hh, hr = rq.rq_hess_blocks(circ, tgt, prob.gates, range=(-1, j0, width),
+                                             chunk=chunk)
+        hh = _np(hh)
+        for (p, a, b) in [(0, 0, 0), (35, 1, 2), (71, 3, 3), (50, 2, 0)]:
+            col = _oracle_hessian_column(k, prob.pairs, prob.gates, prob.param_of, full, cols,
+                                         p, a, b, False)
+            got = hh[:, :, p, 4 * a + b].reshape(-1, 16)
+            assert rel(got, col) <= HESS_TOL[dtype] * 10, (j0, p, a, b, rel(got, col))
+    # one trust-region step on the last range's Hessian (host FP64, both sides)
+    gvec = O.gradient_real(prob.gates, _np(eg))
+    H = _np(hr)
+    delta = np.sqrt(H.shape[0]) * np.pi / 8
+    eta, cand, md, stop = rq.rq_tr_step(prob.gates, gvec, H, delta)
+    # the step depends on (gates, g, H, delta) only; the candidate's cost is
+    # not compared here
+    ref = O.tr_step(prob.gates, float(f), gvec, H, delta, lambda G: 0.0)
+    assert rel(eta, ref["eta"]) <= 1e-10
+    assert rel(cand, ref["candidate"]) <= 1e-10
+    assert abs(md - ref["model_decrease"]) <= 1e-10 * max(1.0, abs(ref["model_decrease"]))
