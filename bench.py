@@ -71,26 +71,38 @@ def gpu_run(rq, torch, circ, target, prob, steps, warmup, chunk, basis_range=Non
     return dict(seconds=t1 - t0, lat_ms=lat, prof=prof, result=res, ws_bytes=ws_need)
 
 
-def copy_bandwidth(torch, nbytes=4 << 30, reps=10):
-    """Read+write rate of a plain device copy (torch's copy kernel) of nbytes:
-    the practical HBM rate for streaming kernels on this GPU, reported next
-    to the 8 TB/s datasheet peak."""
+def copy_bandwidth(torch, rq, nbytes=4 << 30, reps=10):
+    """Read+write rate of a plain device copy of nbytes: librq's hand-written
+    streaming copy kernel (rq_stream_copy) over a few grid shapes, best of
+    them, and torch's copy for comparison -- the practical HBM rate for
+    streaming kernels on this GPU, reported next to the 8 TB/s datasheet
+    peak.  Returns (best rate of the own kernel, its shape, torch's rate)."""
     x = torch.empty(nbytes // 8, dtype=torch.complex64, device="cuda")
     x.real.fill_(1.0)
     y = torch.empty_like(x)
-    for _ in range(3):
-        y.copy_(x)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        y.copy_(x)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    def rate(fn):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return 2 * nbytes / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
+
+    best, shape = 0.0, None
+    for unroll in (1, 4, 8):
+        for blocks in (1024, 4096, 16384):
+            r = rate(lambda: rq.rq_stream_copy(y, x, unroll, blocks))
+            if r > best:
+                best, shape = r, dict(unroll=unroll, blocks=blocks)
+    torch_rate = rate(lambda: y.copy_(x))
     del x, y
     torch.cuda.empty_cache()
-    return round(2 * nbytes / (ms / 1e3) / 1e9, 1)
+    return round(best, 1), shape, round(torch_rate, 1)
 
 
 def _pcts(lat_ms):
@@ -99,8 +111,7 @@ def _pcts(lat_ms):
 
 
 def _kernel_name(key):
-    names = {("hess", "sweep"): "k_hess_pass", ("hess", "states"): "k_pass (per-gate states)",
-             ("hess", "hole"): "k_hole"}
+    names = {("hess", "sweep"): "k_hess_pass", ("hess", "states"): "k_pass (per-gate states)"}
     return names.get(key, f"k_pass {key[0]}/{key[1]}")
 
 
@@ -160,70 +171,208 @@ def measured_traffic(kernel_key):
     return float(v) if v else None
 
 
-def cpu_baseline(prob, ncols=2, budget_s=15.0):
+def _oracle_batch(args):
+    """One batch of the CPU baseline (runs in a worker process): the oracle's
+    f, Euclidean gradient T and HVP tangent Tdot summed over the given basis
+    columns, with target columns drawn from a seeded generator."""
+    k, pairs, inst, Z, cols, seed = args
+    import oracle as O
+    rng = np.random.default_rng(seed)
+    E = rng.standard_normal((1 << k, len(cols))) + 1j * rng.standard_normal((1 << k, len(cols)))
+    E /= np.linalg.norm(E, axis=0)
+    t0 = time.perf_counter()
+    O.tangent_T(k, pairs, inst, Z, E, cols)
+    O.cost(k, pairs, inst, E, cols)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(prob, ncols=512, batch=16):
     """The FP64 oracle timed on the host on a bounded sample: f, gradient and
-    HVP contributions of `ncols` basis states of sector 0, extrapolated to the
-    full 2^k-term trace (every summand costs the same)."""
+    HVP contributions (oracle.tangent_T + oracle.cost, dense numpy on full
+    2^k-row states -- the oracle has no sector-compressed path) of `ncols`
+    basis states of parity sector 0, in batches of `batch` columns spread
+    over one single-threaded worker process per host core (at most 16), and
+    extrapolated to the full 2^k-term trace: every summand costs the same.
+    The target columns of the sample are seeded random unit vectors (the
+    oracle's work does not depend on their values; U|j> of the Strang
+    target would cost thousands of gate applications per column to build)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
     import oracle as O
     k = prob.k
     cols = O.sector_columns(k, 0)[:ncols]
-    E = np.zeros((1 << k, ncols), dtype=np.complex128)
-    E[cols, np.arange(ncols)] = 1.0
-    for pair, G in prob.trotter:             # U|j> for the sample (untimed setup)
-        E = O.apply_gate(E, k, pair, G)
     inst = prob.gates[prob.param_of]
     Z = prob.direction[prob.param_of]
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        O.tangent_T(k, prob.pairs, inst, Z, E, cols)
-        O.cost(k, prob.pairs, inst, E, cols)
-        reps += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = (time.perf_counter() - t0) / reps
-    per_col = dt / ncols
     cores = len(os.sched_getaffinity(0))
-    return dict(value=1.0 / (per_col * (1 << k)), unit="evals/s", cores=cores, kind="oracle",
-                sample=f"{ncols} basis states of sector 0 x {reps} repetitions "
-                       f"({dt * reps:.1f} s), extrapolated x{(1 << k) // ncols}")
+    workers = max(1, min(16, cores))
+    tasks = [(k, prob.pairs, inst, Z, cols[b:b + batch], [w_seed, b])
+             for w_seed in (250623775,) for b in range(0, len(cols), batch)]
+    env = {v: os.environ.get(v) for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                          "MKL_NUM_THREADS")}
+    for v in env:
+        os.environ[v] = "1"               # one thread per worker (inherited at spawn)
+    try:
+        t0 = time.perf_counter()
+        with cf.ProcessPoolExecutor(max_workers=workers,
+                                    mp_context=mp.get_context("spawn")) as ex:
+            busy = sum(ex.map(_oracle_batch, tasks))
+        wall = time.perf_counter() - t0
+    finally:
+        for v, val in env.items():
+            if val is None:
+                os.environ.pop(v, None)
+            else:
+                os.environ[v] = val
+    rate_cols = len(cols) / wall                     # columns per second, all workers
+    return dict(value=rate_cols / (1 << k), unit="evals/s", cores=workers, kind="oracle",
+                sample=f"{len(cols)} basis states of parity sector 0 (general-mode 2^{k}-row "
+                       f"states), {len(tasks)} batches of {batch} over {workers} single-threaded "
+                       f"workers: {wall:.1f} s wall ({busy:.1f} s of worker time), "
+                       f"extrapolated x{(1 << k) / len(cols):.0f} to the 2^{k}-state trace",
+                seconds_per_column=round(busy / len(cols), 4))
 
 
-def serving_run(rq, n_requests, rate_hz, seed_requests=None):
-    """Configuration 5: a Poisson stream of f / f+grad / f+grad+HVP requests
-    of mixed size (k = 8..16, depth 3..9), served by the continuous-batching
-    loop in complex64 with FP64 accumulation.  Latency = completion - arrival
-    (end to end, includes the request's target preparation on the device) and
-    completion - admission (evaluation only)."""
+def config4_hessian(rq, torch, circ, target, prob, ncols, chunk=1024):
+    """Configuration 4's Hessian step: all 72 x 72 blocks of 16 x 16 complex
+    entries (1152 x 1152 real Riemannian Hessian, c64 states + FP64
+    accumulation) summed over `ncols` basis states (all 2^16 for the full
+    step, else the first ncols, timed and extrapolated: every basis state
+    costs the same), then one FP64 trust-region step (truncated CG + polar
+    retraction, rq_tr_step) on the resulting gradient and Hessian."""
+    full = 1 << prob.k
+    ncols = min(int(ncols), full)
+    rng = None if ncols == full else (-1, 0, ncols)
+    rq.rq_hess_blocks(circ, target, prob.gates, range=(-1, 0, 64), chunk=64)    # warm-up
+    torch.cuda.synchronize()
+    rq.rq_profile_read()
+    rq.rq_profile_enable(True)
+    t0 = time.perf_counter()
+    f, eg, _, _, hr = rq.rq_hess_blocks(circ, target, prob.gates, range=rng, chunk=chunk,
+                                        holomorphic=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rq.rq_profile_enable(False)
+    prof = rq.rq_profile_read()
+    H = hr.cpu().numpy()
+    g = rq.rq_tangent_coords(prob.gates, eg.cpu().numpy())
+    delta = float(np.sqrt(H.shape[0]) * np.pi / 8)
+    t1 = time.perf_counter()
+    eta, cand, md, stop = rq.rq_tr_step(prob.gates, g, H, delta)
+    dt_tr = time.perf_counter() - t1
+    hdom = ("hess", "sweep")
+    return {
+        "workload": "cfg4 Hessian step: 72 x 72 instance blocks (1152 x 1152 real Riemannian "
+                    "Hessian) over basis states [0, ncols) of 2^16, c64 states + FP64 "
+                    "accumulation, chunk 1024; then one FP64 trust-region step",
+        "ncols": ncols, "seconds": round(dt, 3),
+        "seconds_full_trace": round(dt * full / ncols, 1),
+        "extrapolated": ncols != full,
+        "kernels": {f"{k[0]}/{k[1]}": dict(ms=round(v["ms"], 1), launches=v["launches"],
+                                           GBps=round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1),
+                                           TFLOPs=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2))
+                    for k, v in prof.items()},
+        "roofline": roofline(prof, hdom),
+        "symmetric_rel": float(f"{np.abs(H - H.T).max() / np.abs(H).max():.2e}"),
+        "tr_step": {"seconds": round(dt_tr, 3), "delta": round(delta, 4),
+                    "grad_norm": float(f"{np.linalg.norm(g):.6e}"),
+                    "step_norm": float(f"{np.linalg.norm(eta):.6e}"),
+                    "model_decrease": float(f"{md:.6e}"), "tcg_stop": int(stop)}}
+
+
+def _serve(rq, descs, dtype=None, chunk=4096, max_active=8):
+    """Run a list of configuration-5 request descriptors through the
+    continuous-batching loop; returns (finished requests, batcher, seconds)."""
     import torch
 
-    import workloads as w
     from paper_2506_23775_amd import serving
-    warm = serving.make_gpu_request(dict(rid=10**6, arrival=0.0, k=8, depth=3, U=4.0, t=0.5,
-                                         op="hvp"), rq.RQ_C64)
-    serving.ContinuousBatcher(serving.GpuExecutor(rq.RQ_C64), hbm_budget=1 << 30).run([warm])
-    descs = w.configs.serving_requests(n_requests, rate_hz)
-    reqs = [serving.make_gpu_request(d, rq.RQ_C64) for d in descs]
-    ex = serving.GpuExecutor(rq.RQ_C64, chunk=4096)
-    batcher = serving.ContinuousBatcher(ex, hbm_budget=96 << 30, max_active=8)
+    dtype = rq.RQ_C64 if dtype is None else dtype
+    reqs = [serving.make_gpu_request(d, dtype) for d in descs]
+    batcher = serving.ContinuousBatcher(serving.GpuExecutor(dtype, chunk=chunk),
+                                        hbm_budget=96 << 30, max_active=max_active)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = batcher.run(reqs)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    stats = serving.latency_stats(done)
+    return done, batcher, time.perf_counter() - t0
+
+
+def _latency(done):
+    from paper_2506_23775_amd import serving
     lat = {op: {k: (round(v, 2) if isinstance(v, float) else v) for k, v in st.items()}
-           for op, st in stats.items()}
-    ks = {}
-    for d in descs:
-        ks[str(d["k"])] = ks.get(str(d["k"]), 0) + 1
-    return dict(workload="cfg5: Poisson arrivals of f / f+grad / f+grad+HVP requests, "
-                         "k in {8..16}, brick-wall depth in {3,5,7,9}, Hubbard targets "
-                         "(dense exp(-iHt) for k <= 12, 20-step Strang Trotter on the device "
-                         "beyond), c64 states + FP64 accumulation",
-                requests=len(done), rate_hz=rate_hz, seconds=round(dt, 3),
-                throughput_req_per_s=round(len(done) / dt, 3), k_mix=ks,
-                peak_hbm_GiB=round(batcher.peak_used / 2**30, 2), latency_ms=lat)
+           for op, st in serving.latency_stats(done).items()}
+    by_k = {}
+    for k in sorted({r.k for r in done}):
+        e2e = np.array([r.t_done - r.arrival for r in done if r.k == k]) * 1e3
+        by_k[str(k)] = dict(n=int(e2e.size), p50_ms=round(float(np.percentile(e2e, 50)), 2),
+                            p99_ms=round(float(np.percentile(e2e, 99)), 2))
+    return lat, by_k
+
+
+def _rel_errors(res, ref):
+    """|df| / max(1, |f|) and relative Frobenius errors of the arrays."""
+    out = {"f_rel": float(f"{abs(res['f'] - ref['f']) / max(1.0, abs(ref['f'])):.3e}")}
+    for key in ("egrad", "rgrad", "ehvp", "rhvp"):
+        if key in res and key in ref:
+            nb = np.linalg.norm(ref[key])
+            out[key + "_rel"] = float(f"{np.linalg.norm(res[key] - ref[key]) / (nb or 1.0):.3e}")
+    return out
+
+
+def serving_errors(rq, done, descs, n_sample=4):
+    """Error of served (c64, in the mix) results against the FP64 path on a
+    sample of the requests: each sampled request is served again alone in
+    complex128 (the path the oracle checks in the GPU tests, where the
+    served results are also compared with the oracle directly).  The sample
+    takes requests of the smallest and the largest qubit counts."""
+    by_rid = {r.rid: r for r in done}
+    order = sorted(descs, key=lambda d: (d["k"], d["rid"]))
+    sample = order[:n_sample // 2] + order[len(order) - (n_sample - n_sample // 2):]
+    out = []
+    for d in sample:
+        alone, _, _ = _serve(rq, [{**d, "arrival": 0.0}], dtype=rq.RQ_C128, max_active=1)
+        out.append(dict(rid=d["rid"], k=d["k"], op=d["op"], reference="c128 GPU path, alone",
+                        **_rel_errors(by_rid[d["rid"]].result, alone[0].result)))
+    return out
+
+
+def serving_run(rq, n_requests, rate_hz, saturate_requests=32, saturate_rate=1000.0):
+    """Configuration 5: Poisson streams of f / f+grad / f+grad+HVP requests
+    of mixed size (k = 8..16, depth 3..9), served by the continuous-batching
+    loop in complex64 with FP64 accumulation.  Two runs: `n_requests` at
+    `rate_hz` (open loop, latency under light load) and `saturate_requests`
+    at an arrival rate far above the service rate (all requests queued at
+    once: the throughput is the loop's capacity).  Latency = completion -
+    arrival (end to end, includes the request's target preparation on the
+    device) and completion - admission (evaluation only), per request type
+    and per qubit count.  Sampled results are compared with FP64 references."""
+    from paper_2506_23775_amd import serving
+
+    import workloads as w
+    warm = serving.make_gpu_request(dict(rid=10**6, arrival=0.0, k=8, depth=3, U=4.0, t=0.5,
+                                         op="hvp"), rq.RQ_C64)
+    serving.ContinuousBatcher(serving.GpuExecutor(rq.RQ_C64), hbm_budget=1 << 30).run([warm])
+    res = {"workload": "cfg5: Poisson arrivals of f / f+grad / f+grad+HVP requests, "
+                       "k in {8..16}, brick-wall depth in {3,5,7,9}, Hubbard targets "
+                       "(dense exp(-iHt) for k <= 12, 20-step Strang Trotter on the device "
+                       "beyond), c64 states + FP64 accumulation"}
+    for name, n, rate in (("open_loop", n_requests, rate_hz),
+                          ("saturated", saturate_requests, saturate_rate)):
+        if n <= 0:
+            continue
+        descs = w.configs.serving_requests(n, rate)
+        done, batcher, dt = _serve(rq, descs)
+        lat, by_k = _latency(done)
+        ks = {}
+        for d in descs:
+            ks[str(d["k"])] = ks.get(str(d["k"]), 0) + 1
+        res[name] = dict(requests=len(done), rate_hz=rate, seconds=round(dt, 3),
+                         throughput_req_per_s=round(len(done) / dt, 3), k_mix=ks,
+                         peak_hbm_GiB=round(batcher.peak_used / 2**30, 2), latency_ms=lat,
+                         latency_ms_by_k=by_k)
+        if name == "saturated":
+            res["error_vs_fp64"] = serving_errors(rq, done, descs)
+    return res
 
 
 def main():
@@ -240,6 +389,9 @@ def main():
                     help="random vectors per parity sector in the sampled-trace leg (0: skip)")
     ap.add_argument("--config4", type=int, default=2,
                     help="timed evaluations of configuration 4 (dense gates; 0: skip)")
+    ap.add_argument("--config4-hessian-cols", type=int, default=4096,
+                    help="basis states of the timed configuration-4 Hessian + trust-region "
+                         "step (65536: the full trace; 0: skip)")
     ap.add_argument("--orbits", type=int, default=1,
                     help="1: time the translation-orbit-reduced evaluation (0: skip)")
     ap.add_argument("--hessian", type=int, default=1,
@@ -247,8 +399,10 @@ def main():
     ap.add_argument("--tr-iters", type=int, default=5,
                     help="trust-region iterations in the configuration-2 leg (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=16,
-                    help="requests in the configuration-5 serving leg (0: skip it)")
+                    help="requests of the open-loop configuration-5 serving run (0: skip it)")
     ap.add_argument("--serving-rate", type=float, default=1.0, help="Poisson arrival rate, 1/s")
+    ap.add_argument("--serving-saturate", type=int, default=32,
+                    help="requests of the saturated serving run (arrival rate 1000/s; 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 2 GiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -311,7 +465,10 @@ def main():
     out["roofline"] = roofline(r64["prof"], dom)
     if args.chunk == 4096:
         out["roofline"]["traffic"] = measured_traffic(f"{dom[0]}/{dom[1]}")
-    out["roofline"]["copy_ref_GBps"] = copy_bandwidth(torch)
+    cref, cshape, ctorch = copy_bandwidth(torch, rq)
+    out["roofline"]["copy_ref_GBps"] = cref
+    out["roofline"]["copy_ref"] = dict(kernel="rq_stream_copy (4 GiB, read + write)", **cshape)
+    out["roofline"]["copy_torch_GBps"] = ctorch
 
     if args.hessian:
         # all pairwise Hessian blocks of configuration 3 over the full trace,
@@ -383,9 +540,13 @@ def main():
                                                TFLOPs=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2))
                         for k, v in r4["prof"].items()},
             "roofline": roofline(r4["prof"], dom4)}
-        del t4
-        torch.cuda.empty_cache()
         log(f"[bench] configuration 4: {out['config4']['ms_per_step']} ms/eval")
+        if args.config4_hessian_cols:
+            out["config4_hessian"] = config4_hessian(rq, torch, c4, t4, p4,
+                                                     args.config4_hessian_cols)
+        del t4
+        rq.release_workspaces()
+        torch.cuda.empty_cache()
 
     if args.orbits:
         # extension beyond the paper: one basis state per translation orbit
@@ -482,12 +643,15 @@ def main():
             "accepted": [int(v) for v in hist[:, 4]]}
         del t2
 
-    if args.serving_requests > 0:
+    if args.serving_requests > 0 or args.serving_saturate > 0:
         del tgt64, tgt128
+        rq.release_workspaces()
         torch.cuda.empty_cache()
-        log(f"[bench] serving leg: {args.serving_requests} requests at {args.serving_rate}/s")
-        out["serving"] = serving_run(rq, args.serving_requests, args.serving_rate)
-        log(f"[bench] serving: {out['serving']['throughput_req_per_s']} req/s")
+        log(f"[bench] serving leg: {args.serving_requests} requests at {args.serving_rate}/s, "
+            f"{args.serving_saturate} at saturation")
+        out["serving"] = serving_run(rq, args.serving_requests, args.serving_rate,
+                                     args.serving_saturate)
+        log("[bench] serving done")
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")

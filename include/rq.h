@@ -306,6 +306,48 @@ int rq_tr_accept(double f0, double f1, double model_decrease, double delta,
  * i (E_12 + E_21)/sqrt2). */
 int rq_tangent_basis(uint32_t flags, double *basis);
 
+/* Basis-orbit reduction of the trace sum (an extension of Sec. "Exploiting
+ * translational invariance", which shares Hessian hole pairs between
+ * translated gates, to the sum over basis states).  When the circuit and the
+ * target are invariant under the cyclic qubit translation by `shift`, the
+ * summand of |j> equals that of every translate of |j>, so the trace is the
+ * sum over one representative per orbit weighted by the orbit size w.  With
+ * input states sqrt(w_r)|rep_r> and target columns sqrt(w_r) U|rep_r>
+ * (every output is bilinear in the two), rq_cost / rq_grad / rq_hvp over the
+ * representatives return the full-trace results.
+ *
+ * rq_orbit_reps (host): representatives (the smallest basis index of each
+ * orbit under q -> q + shift, ascending) and orbit sizes as doubles, for all
+ * 2^k basis states (sector -1) or the states of one popcount parity (sector
+ * 0 / 1, representatives as compressed rows j >> 1).  *count: capacity of
+ * reps / weights on input, number of representatives on output; with reps
+ * and weights both NULL only the count is returned.  RQ_EINVAL for bad
+ * arguments or short arrays. */
+int rq_orbit_reps(int32_t n_qubits, int32_t shift, int32_t sector, int64_t *count,
+                  int64_t *reps, double *weights);
+
+/* Workspace bytes of rq_orbit_target for output slabs of `width` columns
+ * (0 on invalid arguments). */
+size_t rq_orbit_workspace_bytes(const rq_circuit *circuit, int64_t width);
+
+/* Fill device slabs with the orbit-weighted input states and target
+ * columns for circuit->shift (which must be nonzero; the circuit's own
+ * invariance is checked as for every call, the target's is the caller's
+ * promise).  target: the full basis-state target of rq_target (no inputs;
+ * every column j < 2^k, or 2^(k-1) per sector, present: ld >= that count).
+ * d_inputs, d_ref: device slabs of the target's dtype, laid out as
+ * [rows][width] (general) or [2][rows][width] (parity: sector s at
+ * s * rows * width), rows = 2^k or 2^(k-1); column r < count of a sector
+ * holds sqrt(w_r)|rep_r> and sqrt(w_r) U|rep_r>, later columns zero.
+ * width >= the largest per-sector count (rq_orbit_reps).  Use the result
+ * as rq_target{dtype, 0, d_ref, width, rows * width, d_inputs, width,
+ * rows * width} with the range (sector -1, 0, width) in parity mode or
+ * (-1, 0, width) otherwise.  Workspace: rq_orbit_workspace_bytes.  The call
+ * uploads the representatives, synchronizes exec->stream once (set-up
+ * call) and enqueues one fill kernel. */
+int rq_orbit_target(const rq_circuit *circuit, const rq_target *target, void *d_inputs,
+                    void *d_ref, int64_t width, const rq_exec *exec);
+
 /* Diagnostics: gate instances per sweep pass chosen by the scheduler for op
  * and dtype.  pass_of[n_gates] (host) receives the pass index of every
  * instance; returns the number of passes (< 0 on error). */

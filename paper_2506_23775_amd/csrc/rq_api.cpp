@@ -1262,6 +1262,127 @@ int rq_profile_read(double *ms, int64_t *launches, double *bytes, double *flops)
   return st;
 }
 
+// ---------------------------------------------------------------------------
+// Basis-orbit reduction
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+// Orbit representatives (smallest index of each orbit) and orbit sizes of
+// the basis states under the cyclic qubit translation q -> q + shift: the
+// k-bit index rotated right by `shift` bits moves qubit q (bit k-1-q) to
+// q + shift.  sector -1: all states; 0/1: states of that popcount parity,
+// reported as compressed rows (index >> 1).
+int orbit_reps(int k, int shift, int sector, std::vector<int64_t> &reps,
+               std::vector<int64_t> &size) {
+  if (k < 2 || k > 30) return fail(RQ_EINVAL, "orbit reduction: n_qubits out of range [2, 30]");
+  if (shift < 1 || shift >= k) return fail(RQ_EINVAL, "orbit reduction: shift must be in [1, n_qubits)");
+  if (sector < -1 || sector > 1) return fail(RQ_EINVAL, "orbit reduction: sector must be -1, 0 or 1");
+  const uint64_t n = uint64_t(1) << k, mask = n - 1;
+  reps.clear();
+  size.clear();
+  for (uint64_t x = 0; x < n; ++x) {
+    if (sector >= 0 && (__builtin_popcountll(x) & 1) != sector) continue;
+    uint64_t y = x;
+    int64_t m = 0;
+    bool minimal = true;
+    do {
+      y = ((y >> shift) | (y << (k - shift))) & mask;
+      ++m;
+      if (y < x) minimal = false;
+    } while (y != x && minimal);
+    if (!minimal) continue;
+    reps.push_back(sector >= 0 ? int64_t(x >> 1) : int64_t(x));
+    size.push_back(m);
+  }
+  return RQ_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int rq_orbit_reps(int32_t n_qubits, int32_t shift, int32_t sector, int64_t *count,
+                  int64_t *reps, double *weights) {
+  if (!count) return fail(RQ_EINVAL, "rq_orbit_reps: count is NULL");
+  std::vector<int64_t> r, m;
+  const int st = orbit_reps(n_qubits, shift, sector, r, m);
+  if (st) return st;
+  const int64_t cap = *count;
+  *count = int64_t(r.size());
+  if (!reps && !weights) return RQ_OK;
+  if (cap < int64_t(r.size())) return fail(RQ_EINVAL, "rq_orbit_reps: output arrays too short");
+  for (size_t i = 0; i < r.size(); ++i) {
+    if (reps) reps[i] = r[i];
+    if (weights) weights[i] = double(m[i]);
+  }
+  return RQ_OK;
+}
+
+size_t rq_orbit_workspace_bytes(const rq_circuit *circuit, int64_t width) {
+  if (check_circuit(circuit)) return 0;
+  if (width < 1) {
+    g_err = "rq_orbit_workspace_bytes: width must be positive";
+    return 0;
+  }
+  const int nsec = (circuit->flags & RQ_PARITY) ? 2 : 1;
+  return align256(size_t(nsec) * size_t(width) * (sizeof(int64_t) + sizeof(double)));
+}
+
+int rq_orbit_target(const rq_circuit *circuit, const rq_target *target, void *d_inputs,
+                    void *d_ref, int64_t width, const rq_exec *exec) {
+  int st = check_circuit(circuit);
+  if (st) return st;
+  if (!circuit->shift) return fail(RQ_EINVAL, "rq_orbit_target: the circuit declares no shift");
+  if (!target || !target->ref) return fail(RQ_EINVAL, "rq_orbit_target: target or target->ref is NULL");
+  if (target->inputs) return fail(RQ_EINVAL, "rq_orbit_target: the target must be the basis-state target (no inputs)");
+  if (target->dtype != RQ_C128 && target->dtype != RQ_C64) return fail(RQ_EINVAL, "rq_orbit_target: bad dtype");
+  if (!d_inputs || !d_ref) return fail(RQ_EINVAL, "rq_orbit_target: output slabs are NULL");
+  if (!exec || !exec->workspace) return fail(RQ_EINVAL, "rq_orbit_target: exec or workspace is NULL");
+  const bool parity = circuit->flags & RQ_PARITY;
+  const int nsec = parity ? 2 : 1;
+  const int k = circuit->n_qubits;
+  const int64_t rows = int64_t(1) << (parity ? k - 1 : k);
+  if (target->ld < rows) return fail(RQ_EINVAL, "rq_orbit_target: target ld must cover every basis column");
+  if (parity && target->sector_stride < rows * target->ld)
+    return fail(RQ_EINVAL, "rq_orbit_target: sector stride smaller than a sector block");
+  std::vector<std::vector<int64_t>> reps(nsec), size(nsec);
+  for (int s = 0; s < nsec; ++s) {
+    st = orbit_reps(k, circuit->shift, parity ? s : -1, reps[s], size[s]);
+    if (st) return st;
+    if (int64_t(reps[s].size()) > width)
+      return fail(RQ_EINVAL, "rq_orbit_target: width " + std::to_string(width) + " < " +
+                                 std::to_string(reps[s].size()) + " representatives");
+  }
+  const size_t need = rq_orbit_workspace_bytes(circuit, width);
+  if (exec->workspace_bytes < need)
+    return fail(RQ_ESPACE, "rq_orbit_target: workspace too small: need " + std::to_string(need));
+  std::vector<int64_t> hr(size_t(nsec) * width, -1);
+  std::vector<double> hw(size_t(nsec) * width, 0.0);
+  for (int s = 0; s < nsec; ++s)
+    for (size_t i = 0; i < reps[s].size(); ++i) {
+      hr[size_t(s) * width + i] = reps[s][i];
+      hw[size_t(s) * width + i] = std::sqrt(double(size[s][i]));
+    }
+  char *ws = static_cast<char *>(exec->workspace);
+  int64_t *d_reps = reinterpret_cast<int64_t *>(ws);
+  double *d_sw = reinterpret_cast<double *>(ws + size_t(nsec) * width * sizeof(int64_t));
+  hipStream_t s = static_cast<hipStream_t>(exec->stream);
+  st = hip_check(hipMemcpyAsync(d_reps, hr.data(), hr.size() * sizeof(int64_t),
+                                hipMemcpyHostToDevice, s), "rq_orbit_target: upload");
+  if (!st)
+    st = hip_check(hipMemcpyAsync(d_sw, hw.data(), hw.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, s), "rq_orbit_target: upload");
+  if (st) return st;
+  // pageable uploads: wait for them before the staging vectors go away
+  st = hip_check(hipStreamSynchronize(s), "rq_orbit_target: synchronize");
+  if (st) return st;
+  if (launch_orbit_fill(target->dtype == RQ_C128, target->ref, target->ld,
+                        parity ? target->sector_stride : 0, d_reps, d_sw, d_inputs, d_ref, nsec,
+                        rows, width, s))
+    return fail(RQ_EHIP, "rq_orbit_target: launch failed");
+  return RQ_OK;
+}
+
 int rq_stream_copy(void *dst, const void *src, size_t bytes, int32_t unroll, int32_t blocks,
                    void *stream) {
   if (!dst || !src) return fail(RQ_EINVAL, "rq_stream_copy: NULL pointer");

@@ -98,6 +98,9 @@ int launch_reduce(const double *slots, int n_inst, int ne, int nslots,
 int launch_zero(double *p, int64_t n, void *stream);
 int launch_stream_copy(void *dst, const void *src, int64_t bytes, int unroll, int blocks,
                        void *stream);
+int launch_orbit_fill(int is_double, const void *ref_in, int64_t ld_in, int64_t sector_stride_in,
+                      const int64_t *reps, const double *sw, void *inputs, void *ref_out,
+                      int nsec, int64_t rows, int64_t width, void *stream);
 int launch_post(int op, int parity, int accumulate, int n_params, int n_inst, const int32_t *param_of,
                 const double *tsum, int ne, const double *fslots, int nslots,
                 const double *gates64, const double *dir64, double *d_f,

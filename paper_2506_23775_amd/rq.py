@@ -63,7 +63,8 @@ EXPORTS = ["rq_workspace_bytes", "rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks
            "rq_hess_workspace_bytes", "rq_apply_circuit", "rq_tr_step", "rq_tr_accept",
            "rq_tangent_coords", "rq_tr_workspace_bytes", "rq_tr_solve",
            "rq_tangent_basis", "rq_plan_passes", "rq_profile_enable", "rq_profile_read",
-           "rq_stream_copy", "rq_hvp_static", "rq_strerror", "rq_last_error"]
+           "rq_stream_copy", "rq_hvp_static", "rq_orbit_reps", "rq_orbit_workspace_bytes",
+           "rq_orbit_target", "rq_strerror", "rq_last_error"]
 
 
 def lib():
@@ -103,6 +104,12 @@ def lib():
     L.rq_profile_enable.argtypes = [C.c_int]
     L.rq_profile_read.argtypes = [dp, C.POINTER(C.c_int64), dp, dp]
     L.rq_stream_copy.argtypes = [P, P, C.c_size_t, C.c_int32, C.c_int32, P]
+    L.rq_orbit_reps.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
+                                C.POINTER(C.c_int64), dp]
+    L.rq_orbit_workspace_bytes.restype = C.c_size_t
+    L.rq_orbit_workspace_bytes.argtypes = [C.POINTER(_Circuit), C.c_int64]
+    L.rq_orbit_target.argtypes = [C.POINTER(_Circuit), C.POINTER(_Target), P, P, C.c_int64,
+                                  C.POINTER(_Exec)]
     L.rq_hvp_static.argtypes = common + [dp, C.POINTER(_Range), P, C.c_uint32,
                                          C.POINTER(C.c_int64), P, P, P, P, P]
     L.rq_strerror.restype = C.c_char_p
@@ -110,6 +117,7 @@ def lib():
     for name in ["rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks", "rq_apply_circuit",
                  "rq_tr_step", "rq_tr_accept", "rq_tangent_basis", "rq_plan_passes",
                  "rq_tangent_coords", "rq_tr_solve", "rq_stream_copy", "rq_hvp_static",
+                 "rq_orbit_reps", "rq_orbit_target",
                  "rq_profile_enable", "rq_profile_read"]:
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -635,64 +643,59 @@ def sampled_target(k: int, n_samples: int, rng: np.random.Generator, *, dtype: i
 
 def translation_orbits(k: int, shift: int, parity: bool = False):
     """Orbit representatives of the basis states under the cyclic qubit
-    translation q -> q + shift, with their orbit sizes.  Returns a list of
-    (compressed columns, weights) per sector (one entry without parity)."""
-    n = 1 << k
-    x = np.arange(n, dtype=np.int64)
-    rot = x.copy()
-    best = x.copy()
-    # rotating the k-bit index right by `shift` bits moves qubit q to
-    # q + shift (qubit q is bit k-1-q)
-    for _ in range(k):
-        rot = ((rot >> shift) | (rot << (k - shift))) & (n - 1)
-        best = np.minimum(best, rot)
-        if np.all(rot == x):
-            break
-    reps, counts = np.unique(best, return_counts=True)
-    if not parity:
-        return [(reps, counts)]
-    par = np.array([bin(int(v)).count("1") & 1 for v in reps])
-    return [(reps[par == p] >> 1, counts[par == p]) for p in (0, 1)]
+    translation q -> q + shift, with their orbit sizes (rq_orbit_reps).
+    Returns a list of (compressed columns, weights) per sector (one entry
+    without parity)."""
+    L = lib()
+    out = []
+    for sector in ((0, 1) if parity else (-1,)):
+        n = C.c_int64(0)
+        _check(L.rq_orbit_reps(k, shift, sector, C.byref(n), None, None), "rq_orbit_reps")
+        reps = np.zeros(n.value, dtype=np.int64)
+        wts = np.zeros(n.value)
+        _check(L.rq_orbit_reps(k, shift, sector, C.byref(n),
+                               reps.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(wts)),
+               "rq_orbit_reps")
+        out.append((reps, wts.astype(np.int64)))
+    return out
 
 
-def orbit_target(circuit: Circuit, target: Target, device="cuda") -> Target:
+def orbit_target(circuit: Circuit, target: Target, stream=None) -> Target:
     """Input states and target columns that reduce the trace sum to one basis
-    state per translation orbit, weighted by the orbit size: summand r starts
-    from sqrt(w_r)|r> and its target column is sqrt(w_r) U|r>, so every
-    output (bilinear in the two) is sum_r w_r (summand of r), which equals
-    the sum over all basis states when the circuit and the target are
-    invariant under circuit.shift (per-parameter outputs sum instances that
-    the translation permutes).  An extension of Sec. "Exploiting
-    translational invariance" from hole pairs to the basis sum.  Use with
+    state per translation orbit, weighted by the orbit size (rq_orbit_target):
+    summand r starts from sqrt(w_r)|r> and its target column is
+    sqrt(w_r) U|r>, so every output (bilinear in the two) is
+    sum_r w_r (summand of r), which equals the sum over all basis states when
+    the circuit and the target are invariant under circuit.shift.  Use with
     range (-1, 0, R) (R = width of the returned slabs; parity sectors are
     padded with zero columns to a common width)."""
     if not circuit.shift:
         raise ValueError("the circuit declares no translation symmetry")
     if target.col_offset != 0 or target.inputs is not None:
         raise ValueError("orbit reduction needs the full target columns")
-    k = circuit.k
-    orbs = translation_orbits(k, circuit.shift, circuit.parity)
-    R = max(len(r) for r, _ in orbs)
-    td = target.ref.dtype
+    L = lib()
+    counts = []
+    for sector in ((0, 1) if circuit.parity else (-1,)):
+        n = C.c_int64(0)
+        _check(L.rq_orbit_reps(circuit.k, circuit.shift, sector, C.byref(n), None, None),
+               "rq_orbit_reps")
+        counts.append(n.value)
+    R = max(counts)
     rows = target.ref.shape[-2]
-    if circuit.parity:
-        inputs = torch.zeros((2, rows, R), dtype=td, device=device)
-        ref = torch.zeros((2, rows, R), dtype=td, device=device)
-        for p, (reps, wts) in enumerate(orbs):
-            m = len(reps)
-            sw = torch.from_numpy(np.sqrt(wts.astype(np.float64))).to(device)
-            idx = torch.from_numpy(reps).to(device)
-            inputs[p, idx, torch.arange(m, device=device)] = sw.to(td)
-            ref[p, :, :m] = target.ref[p].index_select(1, idx) * sw.to(td)[None, :]
-    else:
-        reps, wts = orbs[0]
-        m = len(reps)
-        sw = torch.from_numpy(np.sqrt(wts.astype(np.float64))).to(device)
-        idx = torch.from_numpy(reps).to(device)
-        inputs = torch.zeros((rows, R), dtype=td, device=device)
-        inputs[idx, torch.arange(m, device=device)] = sw.to(td)
-        ref = target.ref.index_select(1, idx) * sw.to(td)[None, :]
-    return Target(ref.contiguous(), target.dtype, circuit.parity, inputs=inputs)
+    shape = (2, rows, R) if circuit.parity else (rows, R)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(s):
+        inputs = torch.empty(shape, dtype=target.ref.dtype, device=target.ref.device)
+        ref = torch.empty(shape, dtype=target.ref.dtype, device=target.ref.device)
+        need = L.rq_orbit_workspace_bytes(C.byref(circuit._c), R)
+        if need == 0:
+            raise RQError(RQ_EINVAL, "rq_orbit_workspace_bytes")
+        ws = Workspace(need)
+    ex = _Exec(ws.ptr, ws.nbytes, 0, s.cuda_stream, 0, 0)
+    t = target.struct()
+    _check(L.rq_orbit_target(C.byref(circuit._c), C.byref(t), inputs.data_ptr(), ref.data_ptr(),
+                             R, C.byref(ex)), "rq_orbit_target")
+    return Target(ref, target.dtype, circuit.parity, inputs=inputs)
 
 
 STAGES = ("fwd", "last", "bwd")

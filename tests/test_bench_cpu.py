@@ -38,3 +38,15 @@ def test_measured_traffic_lookup():
         # otherwise at least the 6 GiB the pass must move (4 slabs read, 2
         # written, 1 GiB each at the benchmark's chunk)
         assert v is None or v >= 0.9 * 6 * 2**30, (key, v)
+
+
+def test_cpu_baseline_batches_over_workers():
+    """The oracle baseline on a small problem: every sampled column is
+    evaluated once, in batches over single-threaded worker processes, and
+    the reported rate is the sample rate scaled to the full trace."""
+    import workloads as w
+    prob = w.make_problem(1)
+    out = bench.cpu_baseline(prob, ncols=32, batch=8)
+    assert out["kind"] == "oracle" and out["unit"] == "evals/s"
+    assert out["value"] > 0 and 1 <= out["cores"] <= 16
+    assert "32 basis states" in out["sample"] and "4 batches of 8" in out["sample"]

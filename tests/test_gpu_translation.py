@@ -150,3 +150,57 @@ def test_orbit_reduced_config3(rq):
         for x, y in zip(red[1:], full[1:]):
             assert rel(x, y) <= tol, (dtype, rel(x, y))
         del tgt, ot
+
+
+def _orbits_bits(k, s):
+    """Orbit representatives (smallest index) and sizes of the basis states
+    under q -> q + s, by explicit bit lists (no library code)."""
+    seen = {}
+    for x in range(1 << k):
+        b = [(x >> (k - 1 - q)) & 1 for q in range(k)]
+        orb = set()
+        for _ in range(k):
+            b = [b[(q - s) % k] for q in range(k)]
+            orb.add(sum(v << (k - 1 - q) for q, v in enumerate(b)))
+        seen[min(orb)] = len(orb)
+    reps = np.array(sorted(seen))
+    return reps, np.array([seen[r] for r in reps])
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("parity", [False, True])
+def test_orbit_target_abi_vs_oracle_weighted_sum(rq, dtype, parity):
+    """rq_orbit_target (orbit representatives filled on the device through
+    the C ABI) followed by rq_hvp equals the oracle's orbit-weighted sum: the
+    oracle evaluates the input states sqrt(w_r)|rep_r> (representatives and
+    weights from explicit bit lists) against U sqrt(w_r)|rep_r>."""
+    rng = np.random.default_rng([105, dtype, parity])
+    k, layers, shift = 8, 4, 2
+    pairs, layer = w.brickwall_pairs(k, layers)
+    gates = (w.parity_haar_gates if parity else w.haar_gates)(rng, layers)
+    direction = w.tangent_direction(rng, gates, parity=parity)
+    U = w.target_unitary(k // 2, 0.5, 1.0, 4.0)
+    circ = rq.Circuit(k, pairs, param_of=layer, parity=parity, shift=shift)
+    tgt = rq.Target.from_dense(U, dtype, parity=parity)
+    ot = rq.orbit_target(circ, tgt)
+    R = ot.ref.shape[-1]
+    got = rq.rq_hvp(circ, ot, gates, direction, range=(-1, 0, R), chunk=64)
+    reps, wts = _orbits_bits(k, shift)
+    Z = np.zeros((1 << k, len(reps)), dtype=complex)
+    Z[reps, np.arange(len(reps))] = np.sqrt(wts)
+    ref = O.evaluate(k, pairs, gates, layer, direction, U @ Z, None, parity=parity, inputs=Z)
+    tol = 1e-12 if dtype == 0 else 1e-5
+    assert abs(float(got[0]) - ref["f"]) <= tol * max(1.0, abs(ref["f"]))
+    for key, x in zip(["egrad", "rgrad", "ehvp", "rhvp"], got[1:]):
+        assert rel(_np(x), ref[key]) <= tol, key
+    # the device slabs hold exactly the weighted representatives
+    inp = _np(ot.inputs)
+    if parity:
+        par = np.array([bin(int(v)).count("1") & 1 for v in reps])
+        for p in (0, 1):
+            rp, wp = reps[par == p] >> 1, wts[par == p]
+            assert np.allclose(inp[p][rp, np.arange(len(rp))], np.sqrt(wp))
+            assert np.count_nonzero(inp[p]) == len(rp)
+    else:
+        assert np.allclose(inp[reps, np.arange(len(reps))], np.sqrt(wts))
+        assert np.count_nonzero(inp) == len(reps)
