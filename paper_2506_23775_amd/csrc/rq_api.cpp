@@ -187,7 +187,10 @@ int make_layout(const rq_circuit *c, int32_t op_pub, int32_t dtype, int64_t chun
   L.chunk = chunk;
   L.rows = int64_t(1) << L.kq;
   std::string err;
-  if (!plan_passes(c->n_qubits, c->n_gates, c->pairs, L.parity, L.nt, kMaxGates, L.plan, err))
+  // dense complex64 HVP passes take at most 8 gates (their accumulators
+  // share the LDS with the resident forward states; see PassGates)
+  const int maxg = (!L.is_double && !L.parity && op == OP_HVP) ? 8 : kMaxGates;
+  if (!plan_passes(c->n_qubits, c->n_gates, c->pairs, L.parity, L.nt, maxg, L.plan, err))
     return fail(RQ_EINVAL, err);
   const int N = c->n_gates, P = c->n_params;
   const int np = (int)L.plan.size();

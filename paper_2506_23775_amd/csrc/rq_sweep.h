@@ -733,22 +733,34 @@ struct Prefetch {
                                               : (OP == OP_HVP ? 0xf : 0x3);
 };
 
+// Gate cap of a pass: dense complex64 HVP passes keep at most 8 gates, so
+// that their FP64 accumulators (one row of entries per gate, in LDS next to
+// the resident states) leave room for two wavefronts per SIMD; the scheduler
+// applies the same cap.
+template <typename R, int MODE, int OP>
+struct PassGates {
+  static constexpr int value =
+      (MODE == MODE_DENSE && OP == OP_HVP && sizeof(R) == 4) ? 8 : kMaxGates;
+};
+
 // Backward passes that keep the forward states (checkpoint psi, dpsi) in LDS
 // for the whole tile -- loaded there by direct global->LDS loads, un-applied
 // block by block in place -- so that only phi (+dphi) and the contraction
 // partials occupy registers: two wavefronts per SIMD where the LDS allows it
-// (complex64 HVP, gradients), else one, which still lets complex128 HVP run
-// 4-qubit tiles without spills.  Their LDS holds exactly the checkpoint slabs
-// of Prefetch (no look-ahead tile).
+// (complex64 HVP and gradients, parity and dense gates), else one, which
+// still lets complex128 parity HVP run 4-qubit tiles without spills.  Their
+// LDS holds exactly the checkpoint slabs of Prefetch (no look-ahead tile).
 template <typename R, int NT, int MODE, int OP>
 struct Resident {
-  static constexpr bool value = MODE == MODE_PARITY && (OP == OP_GRAD || OP == OP_HVP);
+  static constexpr bool value =
+      (MODE == MODE_PARITY || sizeof(R) == 4) && (OP == OP_GRAD || OP == OP_HVP);
   // the fused last pass too, for the HVP (whose backward half holds four
   // states); the gradient's last pass peaks in its forward half
   static constexpr bool last = value && OP == OP_HVP;
+  static constexpr int NE = (MODE == MODE_DENSE ? 32 : 16) * (OP == OP_HVP ? 2 : 1);
   // LDS per wavefront: the resident states and the contraction accumulators
   static constexpr int lds_bytes = (OP == OP_HVP ? 2 : 1) * (1 << NT) * 64 * int(2 * sizeof(R)) +
-                                   kMaxGates * (OP == OP_HVP ? 32 : 16) * 8;
+                                   PassGates<R, MODE, OP>::value * NE * 8;
   // two wavefronts per SIMD when 8 of them fit the 160 KB of LDS of a CU
   static constexpr int waves = lds_bytes <= 20480 ? 2 : 1;
 };
@@ -807,7 +819,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((
   const int nwaves = gridDim.x * wpb;
   char *pf = reinterpret_cast<char *>(lds);       // PF: this wavefront's tile buffer
   double *acc = reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + PF_BYTES) +
-                wib * (kMaxGates * NE);
+                wib * (PassGates<R, MODE, OP>::value * NE);
   const int my_e = entry_of_lane(lane, LV);
   const bool writer = entry_writer(lane, LV);
   if constexpr (NEEDB) {
@@ -1113,6 +1125,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((
 // ----------------------------------------------------------------------------
 template <typename R, int NT, int MODE, int OP, int STAGE>
 static int launch_one(const PassArgs &a, int grid, void *stream) {
+  if (a.ngates > PassGates<R, MODE, OP>::value) return -1;
   constexpr bool HV = OP == OP_HVP;
   constexpr bool NEEDB = STAGE != ST_FWD && (OP == OP_GRAD || OP == OP_HVP);
   constexpr int NT1 = MODE == MODE_DENSE ? 32 : 16;
@@ -1123,11 +1136,12 @@ static int launch_one(const PassArgs &a, int grid, void *stream) {
     // wavefronts (and slot indices) as grid blocks of 256 threads
     constexpr int NPF = __builtin_popcount(Prefetch<R, NT, MODE, OP>::mask);
     const size_t lds = size_t(NPF) * (1 << NT) * 64 * sizeof(cx<R>) +
-                       size_t(kMaxGates) * NE * sizeof(double);
+                       size_t(PassGates<R, MODE, OP>::value) * NE * sizeof(double);
     hipLaunchKernelGGL((k_pass<R, NT, MODE, OP, STAGE>), dim3(grid * (kBlock / 64)), dim3(64),
                        lds, (hipStream_t)stream, a);
   } else {
-    const size_t lds = NEEDB ? size_t(kBlock / 64) * kMaxGates * NE * sizeof(double) : 0;
+    const size_t lds =
+        NEEDB ? size_t(kBlock / 64) * PassGates<R, MODE, OP>::value * NE * sizeof(double) : 0;
     hipLaunchKernelGGL((k_pass<R, NT, MODE, OP, STAGE>), dim3(grid), dim3(kBlock), lds,
                        (hipStream_t)stream, a);
   }
