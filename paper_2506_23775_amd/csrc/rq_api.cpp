@@ -24,6 +24,7 @@ int launch_copy_cols(int is_double, const void *src, int64_t ld_src, int64_t col
 int launch_onehot(int is_double, void *dst, int64_t rows, int64_t ld, int64_t col0, int ncols,
                   void *s);
 int launch_accum_rows(const double *slots, int rows, int nslots, double *acc, void *s);
+int launch_state_pass(int is_double, int nt, int mode, const StateArgs &a, int grid, void *s);
 int launch_zero_cols(int is_double, void *p, int64_t n, int64_t rows, int64_t ld, int c0, int c1,
                      void *s);
 int launch_hess_post(int N, int P, int structure, const double *hh, const int32_t *inst_off,
@@ -831,15 +832,6 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
         if (!found) return fail(RQ_EHIP, "internal: a translation class of hole pairs is not covered");
       }
   }
-  std::vector<PlanPass> single(N);
-  for (int g = 0; g < N; ++g) {
-    std::vector<PlanPass> pp;
-    if (!plan_passes(c->n_qubits, 1, c->pairs + 2 * g, L.parity, 2, 1, pp, err) || pp.size() != 1)
-      return fail(RQ_EINVAL, err);
-    single[g] = pp[0];
-    single[g].gates[0].inst = (int16_t)g;
-  }
-
   // upload: G and G^T coefficients, FP64 gates, tangent basis, instance lists
   st = prepare_upload(c, L, gates, nullptr);
   if (st) return st;
@@ -886,11 +878,6 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
   char *arr = ws + H.off_arr;
   auto slab = [&](char *b, int i) -> char * { return b + size_t(i) * H.slab_bytes; };
 
-  PassArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.kq = L.kq;
-  a.ld = H.chunk;
-  a.ld_src = H.chunk;
   HessArgs ha;
   std::memset(&ha, 0, sizeof(ha));
   ha.coef = ws + H.off_coef;
@@ -906,18 +893,12 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
 
   for (int si = 0; si < R.nsec; ++si) {
     const int sector = R.sectors[si];
-    a.sector = sector;
     ha.sector = sector;
     const char *ref = static_cast<const char *>(t->ref) + size_t(sector) * size_t(t->sector_stride) * L.esize;
     for (int64_t j0 = R.begin; j0 < R.begin + R.count; j0 += H.chunk) {
       const int ncols = (int)std::min<int64_t>(H.chunk, R.begin + R.count - j0);
       const int ncg = (ncols + 63) / 64;
-      a.col0 = j0;
-      a.ncols = ncols;
-      a.ncg = ncg;
-      a.n_items = (int)((int64_t(1) << (L.kq - 2)) * ncg);
       const double slab_amps = double(H.rows) * double(ncols);  // amplitudes per state slab
-      const int grid2 = (int)((std::min<int64_t>(a.n_items, kMaxWaves) + 3) / 4);
       // psi before every gate along pi (slab t = before the t-th gate of pi),
       // starting from |j> or from the input states
       if (t->inputs) {
@@ -929,32 +910,66 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
       } else if (launch_onehot(L.is_double, slab(psi, 0), H.rows, H.chunk, j0, ncols, s)) {
         return fail(RQ_EHIP, "onehot launch failed");
       }
-      a.coef = ws + H.off_coef;
-      for (int t = 1; t < N; ++t) {
-        fill_pass(a, single[order[t - 1]], L);
-        a.src_psi = slab(psi, t - 1);
-        a.dst_psi = slab(psi, t);
-        if (prof_launch(s, 13, slab_amps * 2 * L.esize, slab_amps * (L.parity ? 16 : 32),
-                        [&] { return launch_pass(L.is_double, 2, L.parity, OP_COST, ST_FWD, a, grid2, s); }))
-          return fail(RQ_EHIP, "forward state launch failed");
+      // one launch per pass of pi: the tile runs through the pass's gates
+      // and is stored before every swept hole gate and at the pass boundary
+      StateArgs sa;
+      std::memset(&sa, 0, sizeof(sa));
+      sa.ld = H.chunk;
+      sa.ncols = ncols;
+      sa.ncg = ncg;
+      sa.kq = L.kq;
+      sa.sector = sector;
+      sa.n_items = (int)((int64_t(1) << (L.kq - H.nt)) * ncg);
+      const int grids = (int)((std::min<int64_t>(sa.n_items, kMaxWaves) + 3) / 4);
+      auto state_pass = [&](const PlanPass &pp) {
+        sa.qmask = pp.qmask;
+        for (int b = 0; b < 8; ++b) sa.pos[b] = pp.pos[b];
+        sa.ngates = (int)pp.gates.size();
+        int stores = 0;
+        for (int g = 0; g <= sa.ngates; ++g) stores += sa.dst[g] != nullptr;
+        return prof_launch(s, 13, slab_amps * (1 + stores) * L.esize,
+                           slab_amps * sa.ngates * (L.parity ? 16 : 32),
+                           [&] { return launch_state_pass(L.is_double, H.nt, L.parity, sa, grids, s); });
+      };
+      // psi before the t-th gate of pi (slab t), where a hole is swept, and at
+      // every pass boundary (the next pass's input)
+      sa.coef = ws + H.off_coef;
+      for (size_t i = 0; i < full.size(); ++i) {
+        const PlanPass &pp = full[i];
+        const int t0 = ppos[pp.gates[0].inst];
+        const int ng = (int)pp.gates.size();
+        sa.src = slab(psi, t0);
+        for (int g = 0; g <= kMaxGates; ++g) sa.dst[g] = nullptr;
+        for (int g = 1; g < ng; ++g)
+          if (sweep[order[t0 + g]]) sa.dst[g] = slab(psi, t0 + g);
+        if (t0 + ng < N) sa.dst[ng] = slab(psi, t0 + ng);
+        for (int g = 0; g < ng; ++g) sa.gates[g] = pp.gates[g];
+        if (state_pass(pp)) return fail(RQ_EHIP, "forward state launch failed");
       }
-      // phi at the output side of every gate along pi (slab = instance); the
-      // passes write valid columns only, and the Hessian sweep reads whole
-      // 64-column groups of phi: zero the padding of a ragged last group
+      // phi at the output side of every gate along pi (slab = instance): the
+      // passes in reverse, each gate's transpose in reverse order.  They
+      // write valid columns only, and the Hessian sweep reads whole 64-column
+      // groups of phi: zero the padding of a ragged last group first.
       if (ncols % 64 &&
           launch_zero_cols(L.is_double, phi, N, H.rows, H.chunk, ncols, ncg * 64, s))
         return fail(RQ_EHIP, "padding launch failed");
       if (launch_copy_cols(L.is_double, ref, t->ld, j0, slab(phi, order[N - 1]), H.rows, H.chunk,
                            ncols, true, s))
         return fail(RQ_EHIP, "target launch failed");
-      a.coef = ws + H.off_coefT;
-      for (int t = N - 1; t >= 1; --t) {
-        fill_pass(a, single[order[t]], L);
-        a.src_psi = slab(phi, order[t]);
-        a.dst_psi = slab(phi, order[t - 1]);
-        if (prof_launch(s, 13, slab_amps * 2 * L.esize, slab_amps * (L.parity ? 16 : 32),
-                        [&] { return launch_pass(L.is_double, 2, L.parity, OP_COST, ST_FWD, a, grid2, s); }))
-          return fail(RQ_EHIP, "backward state launch failed");
+      sa.coef = ws + H.off_coefT;
+      for (size_t i = full.size(); i-- > 0;) {
+        const PlanPass &pp = full[i];
+        const int t0 = ppos[pp.gates[0].inst];
+        const int ng = (int)pp.gates.size();
+        sa.src = slab(phi, order[t0 + ng - 1]);
+        for (int g = 0; g <= kMaxGates; ++g) sa.dst[g] = nullptr;
+        for (int g = 0; g < ng; ++g) {
+          sa.gates[g] = pp.gates[ng - 1 - g];
+          // before reversed gate g (g >= 1): phi after gate t0 + ng - 1 - g
+          if (g >= 1) sa.dst[g] = slab(phi, order[t0 + ng - 1 - g]);
+        }
+        if (t0 > 0) sa.dst[ng] = slab(phi, order[t0 - 1]);
+        if (state_pass(pp)) return fail(RQ_EHIP, "backward state launch failed");
       }
       // hole-array sweeps: hole at the t-th gate of pi, then the rest of its
       // pass and every later pass.  A block of four wavefronts takes four
@@ -965,8 +980,14 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
       ha.ncg = ncg;
       ha.n_rest = (int)((int64_t(1) << (L.kq - H.nt)) * ncg);
       ha.nquads = (H.nd + 3) / 4;
+      // at most the blocks resident at once (a second, partial round of
+      // blocks would run on part of the device), at most one slot per
+      // wavefront, whole item groups of nquads blocks
+      const int resident = launch_hess_pass(L.is_double, H.nt, L.parity, ha, -1, s);
+      if (resident <= 0) return fail(RQ_EHIP, "Hessian sweep occupancy query failed");
+      const int64_t blocks = std::min<int64_t>(resident, kHessSlots / 4);
       const int gridh =
-          ha.nquads * (int)std::min<int64_t>(ha.n_rest, kHessSlots / 4 / ha.nquads);
+          ha.nquads * (int)std::max<int64_t>(1, std::min<int64_t>(ha.n_rest, blocks / ha.nquads));
       const int rows_all = N * H.nd * H.ne;
       for (int t = 0; t + 1 < N; ++t) {
         const int h = order[t];

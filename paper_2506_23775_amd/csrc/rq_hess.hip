@@ -280,6 +280,71 @@ __global__ __launch_bounds__(kBlock) void k_hess_pass(const HessArgs A) {
     }
 }
 
+// States along the fused gate order: a wavefront carries the 2^NT amplitudes
+// of its 64 columns on the pass's tile through the listed gates and stores
+// the tile wherever a destination slab is given (before each gate, after the
+// last), so a pass reads its input once instead of once per gate.
+template <typename R, int NT, int MODE>
+__global__ __launch_bounds__(kBlock) void k_state_pass(const StateArgs A) {
+  constexpr int NA = 1 << NT;
+  constexpr uint32_t ES = sizeof(cx<R>);
+  using K = Codes<MODE, NT>;
+  const int lane = threadIdx.x & 63;
+  const int gwave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * (kBlock / 64);
+  ccoef_t<R> *coef = as_const_coef<R>(A.coef);
+  int64_t bstep[NT];
+  static_for<0, NT>([&](auto B) __attribute__((always_inline)) {
+    bstep[CV(B)] = (int64_t(1) << A.pos[CV(B)]) * A.ld * ES;
+  });
+  auto boff = [&](auto I) __attribute__((always_inline)) {
+    int64_t o = 0;
+    static_for<0, NT>([&](auto B) __attribute__((always_inline)) {
+      if constexpr ((CV(I) >> CV(B)) & 1) o += bstep[CV(B)];
+    });
+    return o;
+  };
+  for (int item = gwave; item < A.n_items; item += nwaves) {
+    const int cg = item % A.ncg;
+    int t = item / A.ncg;
+    const int c = cg * 64 + lane;
+    const bool ok = c < A.ncols;
+    const uint32_t voff = uint32_t(ok ? c : A.ncols - 1) * ES;
+    int64_t base = 0;
+    for (int p = 0; p < A.kq; ++p)
+      if (!((A.qmask >> p) & 1)) {
+        base |= int64_t(t & 1) << p;
+        t >>= 1;
+      }
+    const int pi = MODE == MODE_PARITY ? ((A.sector ^ __builtin_popcountll(base)) & 1) : 0;
+    const int64_t rowb = base * A.ld * ES;
+    const cx<R> zero{R(0), R(0)};
+    cx<R> ps[NA];
+    const char *src = reinterpret_cast<const char *>(A.src) + rowb;
+    static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+      const cx<R> v = ldrow<R>(src + boff(I), voff);
+      ps[CV(I)] = ok ? v : zero;
+    });
+    auto store = [&](void *dst) __attribute__((always_inline)) {
+      if (dst && ok) {
+        char *d = reinterpret_cast<char *>(dst) + rowb;
+        static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+          strow<R>(d + boff(I), voff, ps[CV(I)]);
+        });
+      }
+    };
+    for (int g = 0; g < A.ngates; ++g) {
+      store(A.dst[g]);
+      const GateRef gr = A.gates[g];
+      ccoef_t<R> *co = coef + int64_t(gr.inst) * kCoefStride;
+      dispatch<0, K::n>(gate_code(MODE, NT, gr, pi), [&](auto CC) __attribute__((always_inline)) {
+        fwd_gate<R, NT, MODE, false, CV(CC)>(ps, ps, co);
+      });
+    }
+    store(A.dst[A.ngates]);
+  }
+}
+
 // Columns col0..col0+ncols of a slab (row stride ld_src) into a chunk slab,
 // conjugated for phi = conj(U|j>) at the output side of the last gate; zero in
 // padding columns.
@@ -492,14 +557,49 @@ __global__ __launch_bounds__(256) void k_hess_post(
 // Host launchers.
 // ---------------------------------------------------------------------------
 template <typename R, int NT, int MODE>
-static int launch_hess_one(const HessArgs &a, int grid, void *s) {
+static size_t hess_lds() {
   constexpr int NE = MODE == MODE_DENSE ? 32 : 16;
   // phi double buffer [2][2^NT][64] and the wavefronts' FP64 accumulators
-  const size_t lds = size_t(2) * (1 << NT) * 64 * sizeof(cx<R>) +
-                     size_t(kBlock / 64) * kMaxGates * NE * sizeof(double);
+  return size_t(2) * (1 << NT) * 64 * sizeof(cx<R>) +
+         size_t(kBlock / 64) * kMaxGates * NE * sizeof(double);
+}
+
+// grid < 0: return the number of blocks that are resident on the device at
+// once (compute units x blocks per compute unit of this instantiation);
+// otherwise launch.
+template <typename R, int NT, int MODE>
+static int launch_hess_one(const HessArgs &a, int grid, void *s) {
+  if (grid < 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (k_hess_pass<R, NT, MODE>), kBlock,
+                                                     hess_lds<R, NT, MODE>()) != hipSuccess)
+      return -1;
+    return cus * per_cu;
+  }
+  const size_t lds = hess_lds<R, NT, MODE>();
   hipLaunchKernelGGL((k_hess_pass<R, NT, MODE>), dim3(grid), dim3(kBlock), lds, (hipStream_t)s,
                      a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename R, int NT, int MODE>
+static int launch_state_one(const StateArgs &a, int grid, void *s) {
+  hipLaunchKernelGGL((k_state_pass<R, NT, MODE>), dim3(grid), dim3(kBlock), 0, (hipStream_t)s, a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_state_pass(int is_double, int nt, int mode, const StateArgs &a, int grid, void *s) {
+  if (!is_double) {
+    if (nt == 5 && mode) return launch_state_one<float, 5, 1>(a, grid, s);
+    if (nt == 4) return mode ? launch_state_one<float, 4, 1>(a, grid, s) : launch_state_one<float, 4, 0>(a, grid, s);
+    if (nt == 2) return mode ? launch_state_one<float, 2, 1>(a, grid, s) : launch_state_one<float, 2, 0>(a, grid, s);
+  } else {
+    if (nt == 4) return mode ? launch_state_one<double, 4, 1>(a, grid, s) : launch_state_one<double, 4, 0>(a, grid, s);
+    if (nt == 2) return mode ? launch_state_one<double, 2, 1>(a, grid, s) : launch_state_one<double, 2, 0>(a, grid, s);
+  }
+  return -3;
 }
 
 int launch_hess_pass(int is_double, int nt, int mode, const HessArgs &a, int grid, void *s) {

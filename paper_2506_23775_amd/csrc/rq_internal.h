@@ -86,8 +86,24 @@ struct HessArgs {
   int32_t pos[8];
   GateRef gates[kMaxGates];
 };
-// FP64 partial-sum slots (one per wavefront) of the Hessian sweeps.
-constexpr int kHessSlots = 3072;
+// One pass of the Hessian's per-gate state sweeps (k_state_pass): the tile
+// of src is carried through the gates of the list (coefficients G, or G^T
+// for the backward states), storing the tile before gate g to dst[g] and
+// after the last gate to dst[ngates] (NULL: not stored).
+struct StateArgs {
+  const void *coef;
+  const void *src;
+  void *dst[kMaxGates + 1];
+  int64_t ld;
+  int32_t ncols, ncg, kq, n_items, sector, ngates;
+  uint32_t qmask;
+  int32_t pos[8];
+  GateRef gates[kMaxGates];
+};
+
+// FP64 partial-sum slots (one per wavefront) of the Hessian sweeps: four
+// wavefronts per SIMD of 256 compute units.
+constexpr int kHessSlots = 4096;
 
 // Host-side launchers (defined in rq_launch.hip, rq_hess.hip and the sweep
 // instantiation units).
