@@ -150,12 +150,22 @@ def code_hash(path):
     return hashlib.sha256(txt.encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel_key):
-    """HBM bytes per launch of a sweep kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on a copy
-    kernel), or None when the kernel code changed since it was taken."""
-    prof = os.path.join(ROOT, "profiles", "k_pass_hvp_cfg3_c64.txt")
-    src = os.path.join(ROOT, "paper_2506_23775_amd", "csrc", "rq_sweep.h")
+# committed rocprofv3 counter summaries: (profile file, kernel source whose
+# code hash keys the measurement)
+TRAFFIC_PROFILES = {
+    "sweep": ("k_pass_hvp_cfg3_c64.txt", "rq_sweep.h"),
+    "hess": ("k_hess_pass_cfg3_cfg4_c64.txt", "rq_hess.hip"),
+    "cfg4": ("k_pass_hvp_cfg4_c64.txt", "rq_sweep.h"),
+}
+
+
+def measured_traffic(kernel_key, which="sweep"):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on a copy kernel), or
+    None when the kernel code changed since it was taken."""
+    pname, sname = TRAFFIC_PROFILES[which]
+    prof = os.path.join(ROOT, "profiles", pname)
+    src = os.path.join(ROOT, "paper_2506_23775_amd", "csrc", sname)
     if not (os.path.exists(prof) and os.path.exists(src)):
         return None
     sha = code_hash(src)
@@ -272,7 +282,8 @@ def config4_hessian(rq, torch, circ, target, prob, ncols, chunk=1024):
                                            GBps=round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1),
                                            TFLOPs=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2))
                     for k, v in prof.items()},
-        "roofline": roofline(prof, hdom),
+        "roofline": dict(roofline(prof, hdom),
+                         traffic=measured_traffic("cfg4:hess/sweep", "hess")),
         "symmetric_rel": float(f"{np.abs(H - H.T).max() / np.abs(H).max():.2e}"),
         "tr_step": {"seconds": round(dt_tr, 3), "delta": round(delta, 4),
                     "grad_norm": float(f"{np.linalg.norm(g):.6e}"),
@@ -396,6 +407,8 @@ def main():
                     help="1: time the translation-orbit-reduced evaluation (0: skip)")
     ap.add_argument("--hessian", type=int, default=1,
                     help="1: time the configuration-3 Hessian blocks (0: skip)")
+    ap.add_argument("--hessian-number", type=int, default=1,
+                    help="1: also the Hessian with particle-number-conserving gates (0: skip)")
     ap.add_argument("--tr-iters", type=int, default=5,
                     help="trust-region iterations in the configuration-2 leg (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=16,
@@ -498,7 +511,9 @@ def main():
                         for k, v in hprof.items()},
             "roofline": roofline(hprof, hdom),
             "symmetric_rel": float(f"{np.abs(hr - hr.T).max() / np.abs(hr).max():.2e}")}
+        out["hessian"]["roofline"]["traffic"] = measured_traffic("cfg3:hess/sweep", "hess")
         log(f"[bench] Hessian: {dt:.2f} s")
+    if args.hessian and args.hessian_number:
         # the same Hessian with particle-number-conserving gates (6 hole
         # slices instead of 8)
         c3n = rq.Circuit(prob.k, prob.pairs, param_of=prob.param_of, number=True, shift=4)
@@ -517,7 +532,7 @@ def main():
                         "6 x 6 blocks, 6 hole slices), same target and symmetry",
             "seconds": round(dtn, 3),
             "sweep_ms": round(nprof[("hess", "sweep")]["ms"], 1),
-            "speedup_vs_parity_gates": round(dt / dtn, 3)}
+            "speedup_vs_parity_gates": round(out["hessian"]["seconds"] / dtn, 3)}
         log(f"[bench] Hessian (number gates): {dtn:.2f} s")
 
     if args.config4:
@@ -540,6 +555,8 @@ def main():
                                                TFLOPs=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2))
                         for k, v in r4["prof"].items()},
             "roofline": roofline(r4["prof"], dom4)}
+        out["config4"]["roofline"]["traffic"] = measured_traffic(f"cfg4:{dom4[0]}/{dom4[1]}",
+                                                                 "cfg4")
         log(f"[bench] configuration 4: {out['config4']['ms_per_step']} ms/eval")
         if args.config4_hessian_cols:
             out["config4_hessian"] = config4_hessian(rq, torch, c4, t4, p4,
