@@ -252,16 +252,27 @@ def config4_hessian(rq, torch, circ, target, prob, ncols, chunk=1024):
     retraction, rq_tr_step) on the resulting gradient and Hessian."""
     full = 1 << prob.k
     ncols = min(int(ncols), full)
-    rng = None if ncols == full else (-1, 0, ncols)
     rq.rq_hess_blocks(circ, target, prob.gates, range=(-1, 0, 64), chunk=64)    # warm-up
+    P = prob.n_params
+    outs = [torch.zeros(shape, dtype=torch.float64, device="cuda")
+            for shape in ((1,), (P, 4, 4, 2), (P, 4, 4, 2))] + \
+        [None, torch.zeros((16 * P, 16 * P), dtype=torch.float64, device="cuda")]
     torch.cuda.synchronize()
     rq.rq_profile_read()
     rq.rq_profile_enable(True)
+    # the basis states in ranges of `part` columns, each added into the same
+    # outputs (RQ_EXEC_ACCUMULATE; every output is linear in the basis sum),
+    # so that progress is reported between them
+    part = min(ncols, 8192)
     t0 = time.perf_counter()
-    f, eg, _, _, hr = rq.rq_hess_blocks(circ, target, prob.gates, range=rng, chunk=chunk,
-                                        holomorphic=False)
-    torch.cuda.synchronize()
+    for b in range(0, ncols, part):
+        rq.rq_hess_blocks(circ, target, prob.gates, range=(-1, b, min(part, ncols - b)),
+                          chunk=chunk, out=outs, accumulate=True)
+        torch.cuda.synchronize()
+        log(f"[bench] configuration-4 Hessian: basis states [{b}, {b + part}) done, "
+            f"{time.perf_counter() - t0:.1f} s")
     dt = time.perf_counter() - t0
+    f, eg, hr = outs[0], torch.view_as_complex(outs[1]), outs[4]
     rq.rq_profile_enable(False)
     prof = rq.rq_profile_read()
     H = hr.cpu().numpy()

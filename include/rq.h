@@ -159,8 +159,9 @@ typedef struct rq_range {
  * rq_workspace_bytes(circuit, op, dtype, chunk) bytes, 256-byte aligned.
  * chunk: basis columns per sweep (multiple of 64, >= 64).  stream: a
  * hipStream_t (NULL = default stream).  flags: RQ_EXEC_ACCUMULATE makes
- * rq_cost / rq_grad / rq_hvp add their results to the device outputs instead
- * of overwriting them (all outputs are linear in the basis-state sum, so the
+ * rq_cost / rq_grad / rq_hvp / rq_hess_blocks add their results to the device
+ * outputs instead of overwriting them (at fixed gates every output, the real
+ * Riemannian Hessian included, is linear in the basis-state sum, so the
  * partial sums of disjoint ranges add up to the sum over their union). */
 #define RQ_EXEC_ACCUMULATE 1u
 typedef struct rq_exec {

@@ -27,11 +27,11 @@ int launch_accum_rows(const double *slots, int rows, int nslots, double *acc, vo
 int launch_state_pass(int is_double, int nt, int mode, const StateArgs &a, int grid, void *s);
 int launch_zero_cols(int is_double, void *p, int64_t n, int64_t rows, int64_t ld, int c0, int c1,
                      void *s);
-int launch_hess_post(int N, int P, int structure, const double *hh, const int32_t *inst_off,
-                     const int32_t *inst_list, const int32_t *ppos, const int32_t *map,
-                     const double *gates64,
-                     const double *egrad,
+int launch_hess_post(int N, int P, int structure, int accumulate, const double *hh,
+                     const int32_t *inst_off, const int32_t *inst_list, const int32_t *ppos,
+                     const int32_t *map, const double *gates64, const double *egrad,
                      const double *basis, double *hess_holo, double *hess_real, void *s);
+int launch_add(double *dst, const double *src, int64_t n, void *s);
 }  // namespace rqk
 
 namespace {
@@ -1024,15 +1024,23 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
   const int32_t *il = reinterpret_cast<const int32_t *>(ws + H.off_ilist);
   const int32_t *ppd = reinterpret_cast<const int32_t *>(ws + H.off_ppos);
   const int32_t *mapd = reinterpret_cast<const int32_t *>(ws + H.off_map);
-  if (launch_hess_post(N, P, L.parity ? (L.number ? 2 : 1) : 0, hh, ioff, il, ppd, mapd,
+  const int accumulate = (ex->flags & RQ_EXEC_ACCUMULATE) ? 1 : 0;
+  if (launch_hess_post(N, P, L.parity ? (L.number ? 2 : 1) : 0, accumulate, hh, ioff, il, ppd, mapd,
                        reinterpret_cast<const double *>(ws + H.off_g64),
                        eg_int, reinterpret_cast<const double *>(ws + H.off_basis), d_hh, d_hr, s))
     return fail(RQ_EHIP, "Hessian assembly launch failed");
-  if (d_f) st = hip_check(hipMemcpyAsync(d_f, f_int, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
-  if (!st && d_egrad)
-    st = hip_check(hipMemcpyAsync(d_egrad, eg_int, size_t(P) * 32 * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
-  if (!st && d_rgrad)
-    st = hip_check(hipMemcpyAsync(d_rgrad, rg_int, size_t(P) * 32 * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+  // f and the gradients: copied, or added with RQ_EXEC_ACCUMULATE (every
+  // output is linear in the basis-state sum at fixed gates)
+  auto put = [&](double *dst, const double *src, int64_t n) {
+    if (!dst) return RQ_OK;
+    if (accumulate)
+      return launch_add(dst, src, n, s) ? fail(RQ_EHIP, "add launch failed") : RQ_OK;
+    return hip_check(hipMemcpyAsync(dst, src, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s),
+                     "copy");
+  };
+  st = put(d_f, f_int, 1);
+  if (!st) st = put(d_egrad, eg_int, int64_t(P) * 32);
+  if (!st) st = put(d_rgrad, rg_int, int64_t(P) * 32);
   return st;
 }
 

@@ -19,6 +19,8 @@
 // the tile of psi before the hole gate (no separate hole-array pass).
 // Contractions use the FP64 wavefront reduce-scatter and per-wave slots of
 // the gradient.
+#include <algorithm>
+
 #include "rq_sweep.h"
 
 #define CV(x) decltype(x)::value
@@ -430,7 +432,7 @@ struct zc {
 __device__ inline zc zmul(zc a, zc b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
 __global__ __launch_bounds__(256) void k_hess_post(
-    int N, int P, int structure, const double *__restrict__ hh, const int32_t *__restrict__ inst_off,
+    int N, int P, int structure, int accumulate, const double *__restrict__ hh, const int32_t *__restrict__ inst_off,
     const int32_t *__restrict__ inst_list, const int32_t *__restrict__ ppos,
     const int32_t *__restrict__ map, const double *__restrict__ gates64,
     const double *__restrict__ egrad, const double *__restrict__ basis, double *hess_holo,
@@ -480,8 +482,8 @@ __global__ __launch_bounds__(256) void k_hess_post(
     Hh[t] = {sx, sy};
     if (hess_holo) {
       double *o = hess_holo + ((((int64_t(p) * d + e) * P + q) * d + f) * 2);
-      o[0] = sx;
-      o[1] = sy;
+      o[0] = accumulate ? o[0] + sx : sx;
+      o[1] = accumulate ? o[1] + sy : sy;
     }
     // X_p[r][e] = (G_p A_r)[pos(e)], X_q likewise
     const int r = e, pe = epos(f);
@@ -549,7 +551,8 @@ __global__ __launch_bounds__(256) void k_hess_post(
         }
       acc -= tr;
     }
-    hess_real[(int64_t(p) * d + r) * (int64_t(P) * d) + int64_t(q) * d + s] = acc;
+    double *o = hess_real + (int64_t(p) * d + r) * (int64_t(P) * d) + int64_t(q) * d + s;
+    *o = accumulate ? *o + acc : acc;
   }
 }
 
@@ -664,14 +667,27 @@ int launch_accum_rows(const double *slots, int rows, int nslots, double *acc, vo
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_hess_post(int N, int P, int structure, const double *hh, const int32_t *inst_off,
-                     const int32_t *inst_list, const int32_t *ppos, const int32_t *map,
-                     const double *gates64,
-                     const double *egrad, const double *basis, double *hess_holo,
-                     double *hess_real, void *s) {
-  hipLaunchKernelGGL(k_hess_post, dim3(P * P), dim3(256), 0, (hipStream_t)s, N, P, structure, hh,
-                     inst_off, inst_list, ppos, map, gates64, egrad, basis, hess_holo,
-                     hess_real);
+int launch_hess_post(int N, int P, int structure, int accumulate, const double *hh,
+                     const int32_t *inst_off, const int32_t *inst_list, const int32_t *ppos,
+                     const int32_t *map, const double *gates64, const double *egrad,
+                     const double *basis, double *hess_holo, double *hess_real, void *s) {
+  hipLaunchKernelGGL(k_hess_post, dim3(P * P), dim3(256), 0, (hipStream_t)s, N, P, structure,
+                     accumulate, hh, inst_off, inst_list, ppos, map, gates64, egrad, basis,
+                     hess_holo, hess_real);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// dst[i] += src[i] (accumulating Hessian calls: f and the gradients)
+__global__ void k_add(double *__restrict__ dst, const double *__restrict__ src, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    dst[i] += src[i];
+}
+
+int launch_add(double *dst, const double *src, int64_t n, void *s) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_add, dim3(unsigned(std::min<int64_t>((n + 255) / 256, 1024))), dim3(256),
+                     0, (hipStream_t)s, dst, src, n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

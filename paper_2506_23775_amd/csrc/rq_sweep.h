@@ -460,69 +460,97 @@ __device__ __forceinline__ void bwd_gate_l(cx<R> *sps, cx<R> *sdps, int lane, cx
   if constexpr (K::template valid<C>()) {
     constexpr int H = K::template h<C>(), L = K::template l<C>();
     if constexpr (MODE == MODE_DENSE) {
-      cx<R> g[16], gi[16], z[16], giz[16];
-      static_for<0, 16>([&](auto E) __attribute__((always_inline)) {
-        g[CV(E)] = ldco<R>(co, CV(E));
-        gi[CV(E)] = ldco<R>(co, 16 + CV(E));
-        if constexpr (HV) {
-          z[CV(E)] = ldco<R>(co, 32 + CV(E));
-          giz[CV(E)] = ldco<R>(co, 48 + CV(E));
-        }
-      });
-      for_groups<NT, H, L>([&](auto I0, auto I1, auto I2, auto I3) __attribute__((always_inline)) {
-        constexpr int id[4] = {CV(I0), CV(I1), CV(I2), CV(I3)};
-        cx<R> x[4], xd[4], p[4], pd[4];
-        static_for<0, 4>([&](auto A) __attribute__((always_inline)) {
-          constexpr int a = CV(A);
-          cx<R> y = mv2(gi[4 * a], ps(id[0]), gi[4 * a + 1], ps(id[1]));
-          cfma(y, gi[4 * a + 2], ps(id[2]));
-          cfma(y, gi[4 * a + 3], ps(id[3]));
-          x[a] = y;
-          p[a] = ph[id[a]];
+      // Three phases, each with only its own coefficient blocks live (the
+      // four 4x4 blocks of a dense gate do not fit the registers next to the
+      // backward states and partials at two wavefronts per SIMD):
+      // 1. recover the forward states before the gate, in place in LDS:
+      //    x = G^-1 psi, xd = G^-1 dpsi - (G^-1 Z) x;
+      {
+        cx<R> gi[16], giz[16];
+        static_for<0, 16>([&](auto E) __attribute__((always_inline)) {
+          gi[CV(E)] = ldco<R>(co, 16 + CV(E));
+          if constexpr (HV) giz[CV(E)] = ldco<R>(co, 48 + CV(E));
         });
-        if constexpr (HV) {
+        for_groups<NT, H, L>([&](auto I0, auto I1, auto I2, auto I3) __attribute__((always_inline)) {
+          constexpr int id[4] = {CV(I0), CV(I1), CV(I2), CV(I3)};
+          const cx<R> v[4] = {ps(id[0]), ps(id[1]), ps(id[2]), ps(id[3])};
+          cx<R> x[4];
           static_for<0, 4>([&](auto A) __attribute__((always_inline)) {
             constexpr int a = CV(A);
-            cx<R> y = mv2(gi[4 * a], dps(id[0]), gi[4 * a + 1], dps(id[1]));
-            cfma(y, gi[4 * a + 2], dps(id[2]));
-            cfma(y, gi[4 * a + 3], dps(id[3]));
-            cx<R> m = mv2(giz[4 * a], x[0], giz[4 * a + 1], x[1]);
-            cfma(m, giz[4 * a + 2], x[2]);
-            cfma(m, giz[4 * a + 3], x[3]);
-            y.x -= m.x;
-            y.y -= m.y;
-            xd[a] = y;
-            pd[a] = dph[id[a]];
+            cx<R> y = mv2(gi[4 * a], v[0], gi[4 * a + 1], v[1]);
+            cfma(y, gi[4 * a + 2], v[2]);
+            cfma(y, gi[4 * a + 3], v[3]);
+            x[a] = y;
           });
-        }
+          if constexpr (HV) {
+            const cx<R> d[4] = {dps(id[0]), dps(id[1]), dps(id[2]), dps(id[3])};
+            static_for<0, 4>([&](auto A) __attribute__((always_inline)) {
+              constexpr int a = CV(A);
+              cx<R> y = mv2(gi[4 * a], d[0], gi[4 * a + 1], d[1]);
+              cfma(y, gi[4 * a + 2], d[2]);
+              cfma(y, gi[4 * a + 3], d[3]);
+              cx<R> m = mv2(giz[4 * a], x[0], giz[4 * a + 1], x[1]);
+              cfma(m, giz[4 * a + 2], x[2]);
+              cfma(m, giz[4 * a + 3], x[3]);
+              y.x -= m.x;
+              y.y -= m.y;
+              dps(id[a]) = y;
+            });
+          }
+          static_for<0, 4>([&](auto A) __attribute__((always_inline)) { ps(id[CV(A)]) = x[CV(A)]; });
+        });
+      }
+      // 2. the hole contractions T += phi (x) x, Tdot += dphi (x) x + phi (x) xd;
+      for_groups<NT, H, L>([&](auto I0, auto I1, auto I2, auto I3) __attribute__((always_inline)) {
+        constexpr int id[4] = {CV(I0), CV(I1), CV(I2), CV(I3)};
+        cx<R> x[4], xd[4];
+        static_for<0, 4>([&](auto A) __attribute__((always_inline)) {
+          x[CV(A)] = ps(id[CV(A)]);
+          if constexpr (HV) xd[CV(A)] = dps(id[CV(A)]);
+        });
         static_for<0, 16>([&](auto AB) __attribute__((always_inline)) {
           constexpr int a = CV(AB) / 4, b = CV(AB) % 4, e = 2 * CV(AB);
-          cacc(tp[e], tp[e + 1], p[a], x[b]);
+          cacc(tp[e], tp[e + 1], ph[id[a]], x[b]);
           if constexpr (HV) {
-            cacc(tp[TD + e], tp[TD + e + 1], pd[a], x[b]);
-            cacc(tp[TD + e], tp[TD + e + 1], p[a], xd[b]);
-          }
-        });
-        static_for<0, 4>([&](auto A) __attribute__((always_inline)) {
-          constexpr int a = CV(A);
-          cx<R> y = mv2(g[a], p[0], g[4 + a], p[1]);
-          cfma(y, g[8 + a], p[2]);
-          cfma(y, g[12 + a], p[3]);
-          ph[id[a]] = y;
-          ps(id[a]) = x[a];
-          if constexpr (HV) {
-            cx<R> yd = mv2(g[a], pd[0], g[4 + a], pd[1]);
-            cfma(yd, g[8 + a], pd[2]);
-            cfma(yd, g[12 + a], pd[3]);
-            cfma(yd, z[a], p[0]);
-            cfma(yd, z[4 + a], p[1]);
-            cfma(yd, z[8 + a], p[2]);
-            cfma(yd, z[12 + a], p[3]);
-            dph[id[a]] = yd;
-            dps(id[a]) = xd[a];
+            cacc(tp[TD + e], tp[TD + e + 1], dph[id[a]], x[b]);
+            cacc(tp[TD + e], tp[TD + e + 1], ph[id[a]], xd[b]);
           }
         });
       });
+      // 3. the backward states: phi <- G^T phi, dphi <- G^T dphi + Z^T phi.
+      {
+        cx<R> g[16], z[16];
+        static_for<0, 16>([&](auto E) __attribute__((always_inline)) {
+          g[CV(E)] = ldco<R>(co, CV(E));
+          if constexpr (HV) z[CV(E)] = ldco<R>(co, 32 + CV(E));
+        });
+        for_groups<NT, H, L>([&](auto I0, auto I1, auto I2, auto I3) __attribute__((always_inline)) {
+          constexpr int id[4] = {CV(I0), CV(I1), CV(I2), CV(I3)};
+          const cx<R> p[4] = {ph[id[0]], ph[id[1]], ph[id[2]], ph[id[3]]};
+          cx<R> pd[4], y[4], yd[4];
+          if constexpr (HV)
+            static_for<0, 4>([&](auto A) __attribute__((always_inline)) { pd[CV(A)] = dph[id[CV(A)]]; });
+          static_for<0, 4>([&](auto A) __attribute__((always_inline)) {
+            constexpr int a = CV(A);
+            y[a] = mv2(g[a], p[0], g[4 + a], p[1]);
+            cfma(y[a], g[8 + a], p[2]);
+            cfma(y[a], g[12 + a], p[3]);
+            if constexpr (HV) {
+              yd[a] = mv2(g[a], pd[0], g[4 + a], pd[1]);
+              cfma(yd[a], g[8 + a], pd[2]);
+              cfma(yd[a], g[12 + a], pd[3]);
+              cfma(yd[a], z[a], p[0]);
+              cfma(yd[a], z[4 + a], p[1]);
+              cfma(yd[a], z[8 + a], p[2]);
+              cfma(yd[a], z[12 + a], p[3]);
+            }
+          });
+          static_for<0, 4>([&](auto A) __attribute__((always_inline)) {
+            ph[id[CV(A)]] = y[CV(A)];
+            if constexpr (HV) dph[id[CV(A)]] = yd[CV(A)];
+          });
+        });
+      }
     } else {
       constexpr int KD = K::template kind<C>(), PI = K::template pi<C>();
       cx<R> g[8], gi[8], z[8], giz[8];

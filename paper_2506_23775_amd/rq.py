@@ -431,16 +431,22 @@ def rq_hvp_static(circuit: Circuit, target: Target, gates, direction, range=None
 
 
 def rq_hess_blocks(circuit: Circuit, target: Target, gates, range=None, chunk=None,
-                   workspace=None, stream=None, holomorphic=True):
+                   workspace=None, stream=None, holomorphic=True, out=None, accumulate=False):
     """Returns (f, egrad, rgrad, hess_holo [P,d,P,d] complex or None,
-    hess_real [P*d, P*d]) on the device."""
+    hess_real [P*d, P*d]) on the device.  ``out``: float64 device tensors
+    (f [1], egrad [P,4,4,2], rgrad [P,4,4,2], hess_holo [P,d,P,d,2] or None,
+    hess_real [P*d,P*d]) to write, or with ``accumulate`` to add, into."""
     g = _gates_host(gates)
-    ex, ws = _exec(circuit, RQ_OP_HESS, target.dtype, chunk, workspace, stream)
+    ex, ws = _exec(circuit, RQ_OP_HESS, target.dtype, chunk, workspace, stream,
+                   RQ_EXEC_ACCUMULATE if accumulate else 0)
     P = circuit.n_params
     d = 6 if circuit.number else 8 if circuit.parity else 16
-    f, eg, rg = _out((1,)), _out((P, 4, 4, 2)), _out((P, 4, 4, 2))
-    hh = _out((P, d, P, d, 2), holomorphic)
-    hr = _out((P * d, P * d))
+    if out is not None:
+        f, eg, rg, hh, hr = out
+    else:
+        f, eg, rg = _out((1,)), _out((P, 4, 4, 2)), _out((P, 4, 4, 2))
+        hh = _out((P, d, P, d, 2), holomorphic)
+        hr = _out((P * d, P * d))
     t = target.struct()
     _check(lib().rq_hess_blocks(C.byref(circuit._c), C.byref(t), _dptr(g), _range(range),
                                 C.byref(ex), _ptr(f), _ptr(eg), _ptr(rg), _ptr(hh), _ptr(hr)),

@@ -130,3 +130,28 @@ def test_trust_region_step_from_gpu_hessian(rq):
                                    np.linalg.norm(eta))
     assert acc == ref["accepted"] and abs(nd - ref["new_delta"]) < 1e-12
     assert f1 < float(f)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_hessian_accumulates_over_basis_ranges(rq, dtype):
+    """RQ_EXEC_ACCUMULATE: the Hessian (holomorphic blocks, real Riemannian
+    Hessian, f and gradients) over two disjoint basis ranges added into the
+    same outputs equals the call over their union (every output is linear
+    in the basis-state sum at fixed gates)."""
+    import torch
+    prob = w.make_problem(1)
+    circ = rq.Circuit(prob.k, prob.pairs, param_of=prob.param_of)
+    tgt = rq.Target.from_dense(prob.U_ref, dtype)
+    ref = [_np(x) for x in rq.rq_hess_blocks(circ, tgt, prob.gates, chunk=64)]
+    P = prob.n_params
+    outs = [torch.zeros(sh, dtype=torch.float64, device="cuda")
+            for sh in ((1,), (P, 4, 4, 2), (P, 4, 4, 2), (P, 16, P, 16, 2), (16 * P, 16 * P))]
+    for b, n in ((0, 100), (100, 156)):
+        rq.rq_hess_blocks(circ, tgt, prob.gates, range=(-1, b, n), chunk=64, out=outs,
+                          accumulate=True)
+    got = [o.cpu().numpy() for o in outs]
+    got = [got[0][0]] + [g[..., 0] + 1j * g[..., 1] for g in got[1:4]] + [got[4]]
+    tol = 1e-12 if dtype == 0 else 1e-6
+    assert abs(got[0] - ref[0]) <= tol * max(1.0, abs(ref[0]))
+    for a, b in zip(got[1:], ref[1:]):
+        assert rel(a, b) <= tol, rel(a, b)
