@@ -19,6 +19,7 @@ using cd = std::complex<double>;
 
 namespace rqk {
 int launch_hess_pass(int is_double, int nt, int mode, const HessArgs &a, int grid, void *s);
+int hess_block_waves(int nd);
 int launch_copy_cols(int is_double, const void *src, int64_t ld_src, int64_t col0, void *dst,
                      int64_t rows, int64_t ld, int ncols, bool conj, void *s);
 int launch_onehot(int is_double, void *dst, int64_t rows, int64_t ld, int64_t col0, int ncols,
@@ -979,13 +980,14 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
       ha.ncols = ncols;
       ha.ncg = ncg;
       ha.n_rest = (int)((int64_t(1) << (L.kq - H.nt)) * ncg);
-      ha.nquads = (H.nd + 3) / 4;
+      const int wpb = hess_block_waves(H.nd);
+      ha.nquads = (H.nd + wpb - 1) / wpb;
       // at most the blocks resident at once (a second, partial round of
       // blocks would run on part of the device), at most one slot per
       // wavefront, whole item groups of nquads blocks
       const int resident = launch_hess_pass(L.is_double, H.nt, L.parity, ha, -1, s);
       if (resident <= 0) return fail(RQ_EHIP, "Hessian sweep occupancy query failed");
-      const int64_t blocks = std::min<int64_t>(resident, kHessSlots / 4);
+      const int64_t blocks = std::min<int64_t>(resident, kHessSlots / wpb);
       const int gridh =
           ha.nquads * (int)std::max<int64_t>(1, std::min<int64_t>(ha.n_rest, blocks / ha.nquads));
       const int rows_all = N * H.nd * H.ne;

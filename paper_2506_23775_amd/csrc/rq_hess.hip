@@ -133,7 +133,9 @@ __device__ __forceinline__ void slice_entry(int mode, int nd, int mu, int &a, in
   }
 }
 
-template <typename R, int NT, int MODE>
+// W wavefronts per block, one slice each: 4, or 3 for the six slices of
+// particle-number gates (two blocks per item, no idle wavefronts).
+template <typename R, int NT, int MODE, int W>
 __global__ __launch_bounds__(kBlock) void k_hess_pass(const HessArgs A) {
   constexpr int NA = 1 << NT;
   constexpr int NE = MODE == MODE_DENSE ? 32 : 16;
@@ -145,22 +147,22 @@ __global__ __launch_bounds__(kBlock) void k_hess_pass(const HessArgs A) {
   // 32-63), or one row of complex128
   constexpr int ROWS_PER_LOAD = DW == 2 ? 2 : 1;
   constexpr int TOTAL_LOADS = NA / ROWS_PER_LOAD;        // per tile, over the block
-  constexpr int LOADS = (TOTAL_LOADS + 3) / 4;           // per wavefront (at most)
+  constexpr int LOADS = (TOTAL_LOADS + W - 1) / W;       // per wavefront (at most)
   using K = Codes<MODE, NT>;
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
-  const int gwave = blockIdx.x * (kBlock / 64) + wib;
+  const int gwave = blockIdx.x * W + wib;
   cx<R> *phb = reinterpret_cast<cx<R> *>(lds);                       // [2][NA][64]
   double *acc = reinterpret_cast<double *>(phb + 2 * NA * 64) + wib * (kMaxGates * NE);
   const int my_e = entry_of_lane(lane, LV);
   const bool writer = entry_writer(lane, LV);
-  // block -> (slice quad, first item); the four wavefronts of a block take
+  // block -> (slice group, first item); the W wavefronts of a block take
   // four consecutive slices of the same items
   const int quad = blockIdx.x % A.nquads;
   const int rest0 = blockIdx.x / A.nquads;
   const int rstride = gridDim.x / A.nquads;
-  const int mu = quad * 4 + wib;
+  const int mu = quad * W + wib;
   const bool active = mu < A.nd;           // particle-number mode pads 6 slices to 8
   int ea = 0, eb = 0;
   slice_entry(MODE, A.nd, active ? mu : 0, ea, eb);
@@ -197,8 +199,8 @@ __global__ __launch_bounds__(kBlock) void k_hess_pass(const HessArgs A) {
     const char *src = reinterpret_cast<const char *>(A.phi) +
                       int64_t(A.gates[g].inst) * A.slab * ES + rowb + int64_t(cg) * 64 * ES;
     static_for<0, LOADS>([&](auto Q) __attribute__((always_inline)) {
-      const int li = CV(Q) * 4 + wib;        // load index of this wavefront
-      if (TOTAL_LOADS % 4 == 0 || li < TOTAL_LOADS) {
+      const int li = CV(Q) * W + wib;        // load index of this wavefront
+      if (TOTAL_LOADS % W == 0 || li < TOTAL_LOADS) {
         const int r0 = li * ROWS_PER_LOAD;
         // byte offset of local row r (runtime: wib varies over the block)
         int64_t ro = 0;
@@ -559,32 +561,43 @@ __global__ __launch_bounds__(256) void k_hess_post(
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
-template <typename R, int NT, int MODE>
+template <typename R, int NT, int MODE, int W>
 static size_t hess_lds() {
   constexpr int NE = MODE == MODE_DENSE ? 32 : 16;
   // phi double buffer [2][2^NT][64] and the wavefronts' FP64 accumulators
-  return size_t(2) * (1 << NT) * 64 * sizeof(cx<R>) +
-         size_t(kBlock / 64) * kMaxGates * NE * sizeof(double);
+  return size_t(2) * (1 << NT) * 64 * sizeof(cx<R>) + size_t(W) * kMaxGates * NE * sizeof(double);
 }
 
 // grid < 0: return the number of blocks that are resident on the device at
 // once (compute units x blocks per compute unit of this instantiation);
 // otherwise launch.
-template <typename R, int NT, int MODE>
-static int launch_hess_one(const HessArgs &a, int grid, void *s) {
+template <typename R, int NT, int MODE, int W>
+static int launch_hess_w(const HessArgs &a, int grid, void *s) {
   if (grid < 0) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (k_hess_pass<R, NT, MODE>), kBlock,
-                                                     hess_lds<R, NT, MODE>()) != hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (k_hess_pass<R, NT, MODE, W>),
+                                                     W * 64, hess_lds<R, NT, MODE, W>()) !=
+            hipSuccess)
       return -1;
     return cus * per_cu;
   }
-  const size_t lds = hess_lds<R, NT, MODE>();
-  hipLaunchKernelGGL((k_hess_pass<R, NT, MODE>), dim3(grid), dim3(kBlock), lds, (hipStream_t)s,
-                     a);
+  const size_t lds = hess_lds<R, NT, MODE, W>();
+  hipLaunchKernelGGL((k_hess_pass<R, NT, MODE, W>), dim3(grid), dim3(W * 64), lds,
+                     (hipStream_t)s, a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// wavefronts per block: 3 for the 6 slices of particle-number gates, else 4
+int hess_block_waves(int nd) { return nd == 6 ? 3 : 4; }
+
+template <typename R, int NT, int MODE>
+static int launch_hess_one(const HessArgs &a, int grid, void *s) {
+  if constexpr (MODE == MODE_PARITY) {
+    if (a.nd == 6) return launch_hess_w<R, NT, MODE, 3>(a, grid, s);
+  }
+  return launch_hess_w<R, NT, MODE, 4>(a, grid, s);
 }
 
 template <typename R, int NT, int MODE>
