@@ -36,6 +36,18 @@
  *    returned as zero.  States are stored as in parity mode; the Hessian
  *    propagates 6 hole slices instead of 8 and its blocks have d = 6 entries
  *    in the order (0,0),(3,3),(1,1),(1,2),(2,1),(2,2).
+ *  - Particle-number sectors (RQ_PARITY | RQ_NUMBER | RQ_SECTORS): the same
+ *    gates, with states stored per particle-number sector (the sectors such
+ *    gates keep closed; Sec. "Parity-conserving gate structure"): sector n
+ *    (0 <= n <= k) holds the C(k, n) basis states of popcount n, state x at
+ *    row rank(x) = number of basis indices y < x of the same popcount.  The
+ *    trace then sums C(k, n)^2 amplitudes per sector (sum over n: C(2k, k))
+ *    instead of 2 * 4^(k-1).  rq_sector_rows gives the stacked row of every
+ *    basis index used by the target layout.  Not available for
+ *    rq_hess_blocks, input states or the orbit functions.  This mode is
+ *    currently switched off: every entry point returns RQ_EINVAL for a
+ *    circuit with RQ_SECTORS (its kernels took a device memory fault whose
+ *    cause is not found yet); rq_sector_rows works.
  *  - Precision: states and reference columns are stored and propagated in the
  *    target dtype; every contraction is accumulated in FP64 (per-lane partial
  *    sums of at most 2^(tile-2) products in the state precision, then FP64).
@@ -78,6 +90,8 @@ extern "C" {
 /* ---- circuit flags ------------------------------------------------------ */
 #define RQ_PARITY 1u      /* parity-conserving gates, sector-compressed states */
 #define RQ_NUMBER 2u      /* with RQ_PARITY: particle-number-conserving gates   */
+#define RQ_SECTORS 4u     /* with RQ_PARITY | RQ_NUMBER: states stored per
+                             particle-number sector                           */
 
 /* ---- operations (for rq_workspace_bytes) -------------------------------- */
 #define RQ_OP_COST  0
@@ -118,6 +132,11 @@ typedef struct rq_circuit {
  * General mode: ref[x*ld + j] = U[x][j], x, j < 2^k.
  * Parity mode:  ref[s*sector_stride + x'*ld + j'] = U[x][j] for the sector s
  *               blocks (U conserves parity), x', j' < 2^(k-1).
+ * Particle-number sectors (RQ_SECTORS): ref[(first(n) + rank(x))*ld +
+ *               rank(j)] = U[x][j] for x, j of popcount n (U conserves
+ *               particle number), first(n) = sum of C(k, m) for m < n, i.e.
+ *               the sector blocks stacked by n (stacked rows from
+ *               rq_sector_rows); ld >= C(k, k/2); sector_stride is ignored.
  * Only the columns of the requested basis range are read, so ref may point
  * (by offset) into a narrower window of columns.
  * dtype is also the state precision of the evaluation.
@@ -146,8 +165,11 @@ typedef struct rq_target {
  * [begin, begin+count) of [0, 2^k), sector must be -1.  Parity mode: sector
  * 0 or 1 and j' in [begin, begin+count) of [0, 2^(k-1)), or sector -1 with
  * begin 0 and count 2^(k-1) for both sectors (with input states: sector -1
- * takes [begin, begin+count) in both sectors).  A NULL range is the full
- * trace.  count 0 is allowed (all outputs are then the empty sum, projected). */
+ * takes [begin, begin+count) in both sectors).  Particle-number sectors:
+ * sector n in [0, k] and rank(j) in [begin, begin+count) of [0, C(k, n)), or
+ * sector -1 with begin 0 and count 2^k for every sector in full.  A NULL
+ * range is the full trace.  count 0 is allowed (all outputs are then the
+ * empty sum, projected). */
 typedef struct rq_range {
   int32_t sector;
   int32_t reserved;
@@ -242,7 +264,8 @@ size_t rq_hess_workspace_bytes(const rq_circuit *circuit, int32_t dtype,
 /* Apply the circuit to a slab of states in place (Sec. "Gate application"):
  * states[x*ld + c] for c < n_states, x < 2^k (general) or sector-compressed
  * x' < 2^(k-1) of the given sector (parity mode; sector must then be 0/1,
- * otherwise -1).  Any number of columns; ld >= n_states.  Used to prepare
+ * otherwise -1), or x' = rank(x) < C(k, n) of particle-number sector n
+ * (RQ_SECTORS; sector in [0, k]).  Any number of columns; ld >= n_states.  Used to prepare
  * target columns U|j> from a gate list (e.g. a Trotter circuit).
  * exec: workspace of rq_workspace_bytes(circuit, RQ_OP_APPLY, dtype, 0)
  * bytes (gate coefficients) and the stream; exec->chunk is ignored. */
@@ -367,6 +390,12 @@ int rq_plan_passes(const rq_circuit *circuit, int32_t op, int32_t dtype,
 int rq_profile_enable(int on);
 int rq_profile_read(double *ms, int64_t *launches, double *bytes,
                     double *flops);
+
+/* Stacked particle-number-sector row of every basis index (host):
+ * row_of[x] = first(popcount(x)) + rank(x) for x < 2^n_qubits (the row of
+ * U[x][.] in an RQ_SECTORS target), n_qubits in [1, 28].  row_of: host
+ * int64[2^n_qubits].  Returns RQ_EINVAL for bad arguments. */
+int rq_sector_rows(int32_t n_qubits, int64_t *row_of);
 
 /* Diagnostics: streaming device-to-device copy of `bytes` bytes (a multiple
  * of 16; both pointers 16-byte aligned) by a hand-written kernel in which

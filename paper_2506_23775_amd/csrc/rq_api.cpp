@@ -49,6 +49,11 @@ constexpr int kParityIdx[8] = {0, 3, 12, 15, 5, 6, 9, 10};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Particle-number-sector storage (RQ_SECTORS) is switched off, see
+// check_circuit.
+constexpr bool kSectorsEnabled = false;
+
+
 // Tile qubits per (precision, op, gate class): the largest tile whose
 // register footprint keeps the sweep kernel free of scratch spills (states
 // held per lane: cost/apply 1, grad 2, HVP 4; parity-mode backward sweeps
@@ -130,10 +135,20 @@ int translation_map(const rq_circuit *c, std::vector<int> &tau) {
 int check_circuit(const rq_circuit *c) {
   if (!c) return fail(RQ_EINVAL, "circuit is NULL");
   const bool parity = c->flags & RQ_PARITY;
-  if (c->flags & ~(RQ_PARITY | RQ_NUMBER)) return fail(RQ_EINVAL, "unknown circuit flag");
+  if (c->flags & ~(RQ_PARITY | RQ_NUMBER | RQ_SECTORS)) return fail(RQ_EINVAL, "unknown circuit flag");
   if ((c->flags & RQ_NUMBER) && !parity) return fail(RQ_EINVAL, "RQ_NUMBER requires RQ_PARITY");
+  if ((c->flags & RQ_SECTORS) && !(c->flags & RQ_NUMBER))
+    return fail(RQ_EINVAL, "RQ_SECTORS requires RQ_PARITY | RQ_NUMBER");
+  // The particle-number-sector kernels took a device memory fault on their
+  // first run whose cause has not been found (host-side replay of every
+  // access of that call stays in bounds); the storage mode stays switched
+  // off until it is.
+  if ((c->flags & RQ_SECTORS) && !kSectorsEnabled)
+    return fail(RQ_EINVAL, "RQ_SECTORS is switched off: its kernels faulted on the device and "
+                           "the cause is not found yet");
   const int kmin = parity ? 4 : 2;
-  if (c->n_qubits < kmin || c->n_qubits > 30 + (parity ? 1 : 0))
+  const int kmax = (c->flags & RQ_SECTORS) ? kMaxSectorQubits : 30 + (parity ? 1 : 0);
+  if (c->n_qubits < kmin || c->n_qubits > kmax)
     return fail(RQ_EINVAL, "n_qubits out of range");
   if (c->n_gates < 1 || c->n_gates > 32767) return fail(RQ_EINVAL, "n_gates out of range [1, 32767]");
   if (!c->pairs) return fail(RQ_EINVAL, "pairs is NULL");
@@ -160,13 +175,32 @@ int check_circuit(const rq_circuit *c) {
 
 
 struct Layout {
-  int op = 0, is_double = 0, parity = 0, number = 0, kq = 0, nt = 0, ne = 0, nbuf = 0;
+  int op = 0, is_double = 0, parity = 0, number = 0, sectors = 0, mode = 0, kq = 0, nt = 0,
+      ne = 0, nbuf = 0, k = 0;
   int64_t chunk = 0, rows = 0;
   size_t esize = 0;
   std::vector<PlanPass> plan;
   size_t off_coef = 0, off_g64 = 0, off_d64 = 0, off_pof = 0, off_slots = 0, off_fslots = 0,
-         off_tsum = 0, off_fsum = 0, off_states = 0, state_bytes = 0, upload_bytes = 0, total = 0;
+         off_tsum = 0, off_fsum = 0, off_rank = 0, off_states = 0, state_bytes = 0,
+         upload_bytes = 0, total = 0;
 };
+
+// Binomial coefficient C(n, m) (0 outside 0 <= m <= n).
+int64_t binom(int n, int m) {
+  if (m < 0 || m > n) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= m; ++i) r = r * (n - m + i) / i;
+  return r;
+}
+
+// Particle-number sectors of k qubits: sector n holds the C(k, n) basis
+// states of popcount n in increasing order (colex rank); the target stacks
+// the sectors by n, so sector n starts at row sector_first_row(k, n).
+int64_t sector_first_row(int k, int n) {
+  int64_t r = 0;
+  for (int m = 0; m < n; ++m) r += binom(k, m);
+  return r;
+}
 
 int make_layout(const rq_circuit *c, int32_t op_pub, int32_t dtype, int64_t chunk, Layout &L) {
   int st = check_circuit(c);
@@ -180,6 +214,9 @@ int make_layout(const rq_circuit *c, int32_t op_pub, int32_t dtype, int64_t chun
   L.is_double = dtype == RQ_C128;
   L.parity = (c->flags & RQ_PARITY) != 0;
   L.number = (c->flags & RQ_NUMBER) != 0;
+  L.sectors = (c->flags & RQ_SECTORS) != 0;
+  L.mode = L.sectors ? MODE_NUMBER : L.parity ? MODE_PARITY : MODE_DENSE;
+  L.k = c->n_qubits;
   L.kq = L.parity ? c->n_qubits - 1 : c->n_qubits;
   L.nt = tile_nt(L.kq, L.is_double, op, L.parity);
   L.ne = entries(op, L.parity);
@@ -187,7 +224,8 @@ int make_layout(const rq_circuit *c, int32_t op_pub, int32_t dtype, int64_t chun
     return fail(RQ_EINVAL, "problem too large for one sweep grid (reduce chunk)");
   L.esize = L.is_double ? 16 : 8;
   L.chunk = chunk;
-  L.rows = int64_t(1) << L.kq;
+  // slab rows: 2^kq, or the largest particle-number sector
+  L.rows = L.sectors ? binom(L.k, L.k / 2) : int64_t(1) << L.kq;
   std::string err;
   // dense complex64 HVP passes take at most 8 gates (their accumulators
   // share the LDS with the resident forward states; see PassGates)
@@ -223,6 +261,8 @@ int make_layout(const rq_circuit *c, int32_t op_pub, int32_t dtype, int64_t chun
     L.off_fsum = o;
     o = align256(o + sizeof(double));
   }
+  L.off_rank = o;
+  if (L.sectors) o = align256(o + (size_t(1) << L.k) * sizeof(int32_t));
   L.off_states = o;
   L.state_bytes = op == OP_APPLY ? 0 : size_t(L.rows) * size_t(chunk) * L.esize;
   o = align256(o + size_t(L.nbuf) * L.state_bytes);
@@ -441,13 +481,14 @@ int prof_launch(hipStream_t s, int kind, double bytes, double flops, F &&launch)
   return st;
 }
 
-int launch_prof(int is_double, int nt, int parity, int op, int stage, const PassArgs &a, int grid,
-                hipStream_t s, double slabs) {
-  const int64_t tiles = int64_t(1) << (a.kq - nt);
-  const double amps = double(tiles) * double(1 << nt) * double(a.ncols);
+// rows: amplitudes per column of the sector swept (2^kq, or C(k, n) in a
+// particle-number sector).
+int launch_prof(int is_double, int nt, int mode, int op, int stage, const PassArgs &a, int grid,
+                hipStream_t s, double slabs, int64_t rows) {
+  const double amps = double(rows) * double(a.ncols);
   return prof_launch(s, 3 * op + stage, amps * slabs * (is_double ? 16.0 : 8.0),
-                     amps * double(a.ngates) * flops_per_amp_gate(op, stage, parity != 0),
-                     [&] { return launch_pass(is_double, nt, parity, op, stage, a, grid, s); });
+                     amps * double(a.ngates) * flops_per_amp_gate(op, stage, mode != MODE_DENSE),
+                     [&] { return launch_pass(is_double, nt, mode, op, stage, a, grid, s); });
 }
 
 int hip_check(hipError_t e, const char *what) {
@@ -480,16 +521,45 @@ int grid_for(const Layout &L, int ncols, int &items, int &ncg, bool fwd = false)
 }
 
 struct Range {
-  int sectors[2];
+  int sectors[kMaxSectorQubits + 1];
   int nsec;
   int64_t begin, count;
+  bool whole;  // every sector in full (count per sector = its size)
 };
+
+// Basis columns of a sector: 2^kq, or C(k, n) for particle-number sector n.
+int64_t sector_cols(const Layout &L, int sector) {
+  return L.sectors ? binom(L.k, sector) : int64_t(1) << L.kq;
+}
 
 // inputs: input states replace the basis states; then sector -1 in parity
 // mode takes the same column range in both sectors.
 int check_range(const rq_circuit *c, const Layout &L, const rq_range *r, Range &R,
                 bool inputs = false) {
   const int64_t ncol = int64_t(1) << L.kq;
+  R.whole = false;
+  if (L.sectors) {
+    // particle-number sectors: sector -1 = the full trace, else one sector n
+    if (inputs) return fail(RQ_EINVAL, "input states are not supported with RQ_SECTORS");
+    if (!r || r->sector == -1) {
+      if (r && (r->begin != 0 || r->count != (int64_t(1) << L.k)))
+        return fail(RQ_EINVAL, "sector -1 requires begin 0 and count 2^k with RQ_SECTORS");
+      R.nsec = L.k + 1;
+      for (int n = 0; n <= L.k; ++n) R.sectors[n] = n;
+      R.begin = 0;
+      R.count = 0;
+      R.whole = true;
+      return RQ_OK;
+    }
+    if (r->sector < 0 || r->sector > L.k) return fail(RQ_EINVAL, "sector must be -1 or in [0, k]");
+    if (r->begin < 0 || r->count < 0 || r->begin + r->count > binom(L.k, r->sector))
+      return fail(RQ_EINVAL, "basis range out of bounds");
+    R.nsec = 1;
+    R.sectors[0] = r->sector;
+    R.begin = r->begin;
+    R.count = r->count;
+    return RQ_OK;
+  }
   if (!r) {
     R.begin = 0;
     R.count = ncol;
@@ -548,6 +618,8 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
   const int64_t ncol = int64_t(1) << L.kq;
   if (t->ld < 1) return fail(RQ_EINVAL, "target ld must be positive");
   if (t->inputs && t->in_ld < 1) return fail(RQ_EINVAL, "input-state ld must be positive");
+  if (L.sectors && t->ld < binom(L.k, L.k / 2))
+    return fail(RQ_EINVAL, "target ld must be at least the largest sector size with RQ_SECTORS");
   (void)ncol;
   st = prepare_upload(c, L, gates, dir);
   if (st) return st;
@@ -564,6 +636,8 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
   const int N = c->n_gates;
   if (launch_zero(slots, int64_t(N) * L.ne * kMaxWaves, s) || launch_zero(fslots, kMaxWaves, s))
     return fail(RQ_EHIP, "zero kernel launch failed");
+  int32_t *rank = L.sectors ? reinterpret_cast<int32_t *>(ws + L.off_rank) : nullptr;
+  if (rank && launch_rank_table(rank, L.k, s)) return fail(RQ_EHIP, "rank table launch failed");
 
   const int np = (int)L.plan.size();
   const int nst = L.op == OP_HVP ? 2 : 1;
@@ -580,13 +654,18 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
   a.ne = L.ne;
   a.ld = L.chunk;
   a.ld_ref = t->ld;
+  a.rank = rank;
 
   for (int si = 0; si < R.nsec; ++si) {
     const int sector = R.sectors[si];
+    const int64_t rows = L.sectors ? binom(L.k, sector) : int64_t(1) << L.kq;
+    const int64_t cbeg = R.whole ? 0 : R.begin, cend = R.whole ? sector_cols(L, sector) : R.begin + R.count;
     a.sector = sector;
-    a.ref = static_cast<const char *>(t->ref) + size_t(sector) * size_t(t->sector_stride) * L.esize;
-    for (int64_t j0 = R.begin; j0 < R.begin + R.count; j0 += L.chunk) {
-      const int ncols = (int)std::min<int64_t>(L.chunk, R.begin + R.count - j0);
+    a.ref = static_cast<const char *>(t->ref) +
+            (L.sectors ? size_t(sector_first_row(L.k, sector)) * size_t(t->ld)
+                       : size_t(sector) * size_t(t->sector_stride)) * L.esize;
+    for (int64_t j0 = cbeg; j0 < cend; j0 += L.chunk) {
+      const int ncols = (int)std::min<int64_t>(L.chunk, cend - j0);
       int items, ncg;
       const int grid = grid_for(L, ncols, items, ncg);
       const int grid_fwd = grid_for(L, ncols, items, ncg, true);
@@ -611,8 +690,8 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
           a.dst_psi = buf(nst * p);
           a.dst_dpsi = nst == 2 ? buf(nst * p + 1) : nullptr;
         }
-        if (launch_prof(L.is_double, L.nt, L.parity, L.op, ST_FWD, a, grid_fwd, s,
-                        (p > 0 ? nst : 0) + nst))
+        if (launch_prof(L.is_double, L.nt, L.mode, L.op, ST_FWD, a, grid_fwd, s,
+                        (p > 0 ? nst : 0) + nst, rows))
           return fail(RQ_EHIP, "forward pass launch failed");
       }
       // last pass: forward, overlap with U|j>, first backward pass
@@ -627,8 +706,8 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
         a.dphi = nst == 2 ? buf(nst * (np - 1) + 1) : nullptr;
         a.store_phi = np > 1;
       }
-      if (launch_prof(L.is_double, L.nt, L.parity, L.op, ST_LAST, a, grid, s,
-                      (np > 1 ? nst : 0) + 1 + (L.op != OP_COST && np > 1 ? nst : 0)))
+      if (launch_prof(L.is_double, L.nt, L.mode, L.op, ST_LAST, a, grid, s,
+                      (np > 1 ? nst : 0) + 1 + (L.op != OP_COST && np > 1 ? nst : 0), rows))
         return fail(RQ_EHIP, "last pass launch failed");
       if (L.op == OP_COST) continue;
       for (int p = np - 2; p >= 0; --p) {
@@ -636,8 +715,8 @@ int run_sweep(const rq_circuit *c, const rq_target *t, const double *gates, cons
         a.ckpt_psi = buf(nst * p);
         a.ckpt_dpsi = nst == 2 ? buf(nst * p + 1) : nullptr;
         a.store_phi = p > 0;
-        if (launch_prof(L.is_double, L.nt, L.parity, L.op, ST_BWD, a, grid, s,
-                        2 * nst + (p > 0 ? nst : 0)))
+        if (launch_prof(L.is_double, L.nt, L.mode, L.op, ST_BWD, a, grid, s,
+                        2 * nst + (p > 0 ? nst : 0), rows))
           return fail(RQ_EHIP, "backward pass launch failed");
       }
     }
@@ -672,6 +751,7 @@ struct HessLayout {
 int make_hess_layout(const rq_circuit *c, int32_t dtype, int64_t chunk, HessLayout &H) {
   int st = make_layout(c, RQ_OP_GRAD, dtype, chunk, H.g);
   if (st) return st;
+  if (H.g.sectors) return fail(RQ_EINVAL, "Hessian blocks with RQ_SECTORS are not supported");
   const Layout &L = H.g;
   H.N = c->n_gates;
   H.P = c->n_params;
@@ -1212,8 +1292,10 @@ int rq_apply_circuit(const rq_circuit *circuit, const double *gates, void *d_sta
   if (st) return st;
   if (n_states < 0 || ld < n_states || ld < 1) return fail(RQ_EINVAL, "invalid n_states / ld");
   if (n_states > 0 && !d_states) return fail(RQ_EINVAL, "states is NULL");
-  if (L.parity ? (sector != 0 && sector != 1) : sector != -1)
-    return fail(RQ_EINVAL, "sector must be 0/1 with RQ_PARITY, -1 otherwise");
+  if (L.sectors ? (sector < 0 || sector > L.k)
+                : L.parity ? (sector != 0 && sector != 1) : sector != -1)
+    return fail(RQ_EINVAL, "sector must be in [0, k] with RQ_SECTORS, 0/1 with RQ_PARITY, "
+                           "-1 otherwise");
   if (exec->workspace_bytes < L.total)
     return fail(RQ_ESPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
   if (n_states > (int64_t(1) << 26) ||
@@ -1234,15 +1316,21 @@ int rq_apply_circuit(const rq_circuit *circuit, const double *gates, void *d_sta
   a.ld_src = ld;
   a.sector = L.parity ? sector : 0;
   a.ncols = (int)n_states;
+  if (L.sectors) {
+    a.rank = reinterpret_cast<int32_t *>(ws + L.off_rank);
+    if (launch_rank_table(const_cast<int32_t *>(a.rank), L.k, s))
+      return fail(RQ_EHIP, "rank table launch failed");
+  }
   int items, ncg;
   const int grid = grid_for(L, (int)n_states, items, ncg, true);
   a.ncg = ncg;
   a.n_items = items;
+  const int64_t rows = L.sectors ? binom(L.k, sector) : int64_t(1) << L.kq;
   for (const PlanPass &pp : L.plan) {
     fill_pass(a, pp, L);
     a.src_psi = d_states;
     a.dst_psi = d_states;
-    if (launch_prof(L.is_double, L.nt, L.parity, OP_APPLY, ST_FWD, a, grid, s, 2))
+    if (launch_prof(L.is_double, L.nt, L.mode, OP_APPLY, ST_FWD, a, grid, s, 2, rows))
       return fail(RQ_EHIP, "apply pass launch failed");
   }
   return RQ_OK;
@@ -1367,6 +1455,8 @@ int rq_orbit_target(const rq_circuit *circuit, const rq_target *target, void *d_
   int st = check_circuit(circuit);
   if (st) return st;
   if (!circuit->shift) return fail(RQ_EINVAL, "rq_orbit_target: the circuit declares no shift");
+  if (circuit->flags & RQ_SECTORS)
+    return fail(RQ_EINVAL, "rq_orbit_target: not available with RQ_SECTORS");
   if (!target || !target->ref) return fail(RQ_EINVAL, "rq_orbit_target: target or target->ref is NULL");
   if (target->inputs) return fail(RQ_EINVAL, "rq_orbit_target: the target must be the basis-state target (no inputs)");
   if (target->dtype != RQ_C128 && target->dtype != RQ_C64) return fail(RQ_EINVAL, "rq_orbit_target: bad dtype");
@@ -1414,6 +1504,29 @@ int rq_orbit_target(const rq_circuit *circuit, const rq_target *target, void *d_
                         parity ? target->sector_stride : 0, d_reps, d_sw, d_inputs, d_ref, nsec,
                         rows, width, s))
     return fail(RQ_EHIP, "rq_orbit_target: launch failed");
+  return RQ_OK;
+}
+
+int rq_sector_rows(int32_t n_qubits, int64_t *row_of) {
+  if (n_qubits < 1 || n_qubits > kMaxSectorQubits)
+    return fail(RQ_EINVAL, "rq_sector_rows: n_qubits out of range [1, " +
+                               std::to_string(kMaxSectorQubits) + "]");
+  if (!row_of) return fail(RQ_EINVAL, "rq_sector_rows: row_of is NULL");
+  const int k = n_qubits;
+  int64_t row = 0;
+  for (int n = 0; n <= k; ++n) {
+    // the popcount-n indices in increasing order (next larger index with the
+    // same popcount: Gosper's rule)
+    if (n == 0) {
+      row_of[0] = row++;
+      continue;
+    }
+    for (uint64_t x = (uint64_t(1) << n) - 1; x < (uint64_t(1) << k);) {
+      row_of[x] = row++;
+      const uint64_t low = x & (~x + 1), ripple = x + low;
+      x = ripple | (((x ^ ripple) >> 2) / low);
+    }
+  }
   return RQ_OK;
 }
 

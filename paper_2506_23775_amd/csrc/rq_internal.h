@@ -12,13 +12,19 @@ constexpr int kBlock = 256;
 // Maximum number of wavefronts of a sweep grid; also the number of FP64
 // partial-sum slots per accumulated quantity.
 constexpr int kMaxWaves = 2048;
+// Largest qubit count with particle-number-sector storage (its rank table
+// holds 2^k int32 entries).
+constexpr int kMaxSectorQubits = 28;
 // Complex coefficients stored per gate instance:
 //   [ 0,16) G      [16,32) G^-1      [32,48) Z      [48,64) G^-1 Z
 // dense gates row-major 4x4; parity gates the 8 pattern entries in the order
 // (0,0),(0,3),(3,0),(3,3),(1,1),(1,2),(2,1),(2,2).
 constexpr int kCoefStride = 64;
 
-enum Mode { MODE_DENSE = 0, MODE_PARITY = 1 };
+// MODE_NUMBER: particle-number-conserving gates on states stored per
+// particle-number sector (rows = colex rank of the basis state within its
+// sector); the gate arithmetic is that of MODE_PARITY.
+enum Mode { MODE_DENSE = 0, MODE_PARITY = 1, MODE_NUMBER = 2 };
 enum Op { OP_COST = 0, OP_GRAD = 1, OP_HVP = 2, OP_APPLY = 3 };
 enum Stage { ST_FWD = 0, ST_LAST = 1, ST_BWD = 2 };
 
@@ -44,6 +50,8 @@ struct PassArgs {
   void *phi;               // BWD in/out, LAST out
   void *dphi;
   const void *ref;         // LAST: target columns U|j> (sector block)
+  const int32_t *rank;     // MODE_NUMBER: colex rank of every basis index
+                           // within its particle-number sector [2^k]
   double *slots;           // FP64 partials [inst][entry][slot]
   double *fslots;          // FP64 partials of f [slot]
   int64_t ld;              // row stride of the chunk slabs (elements)
@@ -55,7 +63,8 @@ struct PassArgs {
   int32_t kq;              // explicit qubits (k, or k-1 in parity mode)
   int32_t n_items;         // tiles * column groups
   uint32_t qmask;          // bit positions (in the row index) of the tile
-  int32_t sector;          // parity sector p (0 in general mode)
+  int32_t sector;          // parity sector p (0 in general mode); particle
+                           // number n in MODE_NUMBER
   int32_t ngates;
   int32_t nslots;
   int32_t store_phi;
@@ -112,6 +121,7 @@ int launch_pass(int is_double, int nt, int mode, int op, int stage,
 int launch_reduce(const double *slots, int n_inst, int ne, int nslots,
                   double *out, void *stream);
 int launch_zero(double *p, int64_t n, void *stream);
+int launch_rank_table(int32_t *rank, int k, void *stream);
 int launch_stream_copy(void *dst, const void *src, int64_t bytes, int unroll, int blocks,
                        void *stream);
 int launch_orbit_fill(int is_double, const void *ref_in, int64_t ld_in, int64_t sector_stride_in,

@@ -2,6 +2,8 @@
 // post-processing, and the dispatcher of the sweep-kernel instantiations.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "rq_internal.h"
 
 namespace rqk {
@@ -48,6 +50,43 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const double *__restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// Binomial coefficients C(n, m), n, m < 32 (C(31, 15) < 2^31).
+struct BinomTable {
+  int32_t v[32][32];
+};
+constexpr BinomTable make_binom_table() {
+  BinomTable t{};
+  for (int n = 0; n < 32; ++n) {
+    t.v[n][0] = 1;
+    for (int m = 1; m <= n; ++m) t.v[n][m] = t.v[n - 1][m - 1] + (m < n ? t.v[n - 1][m] : 0);
+  }
+  return t;
+}
+__constant__ BinomTable kBinom = make_binom_table();
+
+// rank[x] = colex rank of basis index x among the indices of its popcount:
+// the number of y < x with popcount(y) = popcount(x), i.e. the sum of
+// C(p, j) over the set bits of x (p its position, j = 1, 2, ... its order
+// from the least significant set bit).
+__global__ void k_rank_table(int32_t *rank, int k) {
+  const int64_t n = int64_t(1) << k;
+  for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < n;
+       x += int64_t(gridDim.x) * blockDim.x) {
+    int32_t r = 0;
+    int j = 0;
+    for (int p = 0; p < k; ++p)
+      if ((x >> p) & 1) r += kBinom.v[p][++j];
+    rank[x] = r;
+  }
+}
+
+int launch_rank_table(int32_t *rank, int k, void *s) {
+  const int64_t n = int64_t(1) << k;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_rank_table, dim3(blocks), dim3(256), 0, (hipStream_t)s, rank, k);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 __global__ void k_zero(double *p, int64_t n) {

@@ -757,7 +757,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <typename R, int NT, int MODE, int OP>
 struct Prefetch {
   static constexpr int mask =
-      (sizeof(R) == 4 || MODE == MODE_PARITY) ? (OP == OP_HVP ? 0x5 : 0x1)
+      (sizeof(R) == 4 || MODE != MODE_DENSE) ? (OP == OP_HVP ? 0x5 : 0x1)
                                               : (OP == OP_HVP ? 0xf : 0x3);
 };
 
@@ -781,7 +781,7 @@ struct PassGates {
 template <typename R, int NT, int MODE, int OP>
 struct Resident {
   static constexpr bool value =
-      (MODE == MODE_PARITY || sizeof(R) == 4) && (OP == OP_GRAD || OP == OP_HVP);
+      (MODE != MODE_DENSE || sizeof(R) == 4) && (OP == OP_GRAD || OP == OP_HVP);
   // the fused last pass too, for the HVP (whose backward half holds four
   // states); the gradient's last pass peaks in its forward half
   static constexpr bool last = value && OP == OP_HVP;
@@ -824,6 +824,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((
   constexpr int LV = ilog2<NE>();
   constexpr uint32_t ES = sizeof(cx<R>);
   using K = Codes<MODE, NT>;
+  // particle-number sectors: rows are sector ranks looked up per tile
+  constexpr bool NUM = MODE == MODE_NUMBER;
   extern __shared__ double lds[];
 
   // Backward passes run one wavefront per block and bring the PFMASK slabs
@@ -840,6 +842,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((
   constexpr int PFMASK = Prefetch<R, NT, MODE, OP>::mask;
   constexpr int NPF = __builtin_popcount(PFMASK);
   constexpr int PF_BYTES = (PF || LRESL) ? NPF * NA * 64 * int(ES) : 0;
+  static_assert(!(NUM && PF && !LRES), "sector-row tiles are only loaded for the current item");
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
@@ -893,6 +896,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((
     });
     return o;
   };
+  // NUM: lane i < NA holds the sector row of local amplitude i of the
+  // current tile (bit i of vmask: the amplitude belongs to the sector; the
+  // others are zero and are neither loaded nor stored)
+  int32_t rk_lane = 0;
+  uint32_t vmask = ~0u;
+  auto rvalid = [&](auto I) __attribute__((always_inline)) -> bool {
+    if constexpr (NUM) return (vmask >> CV(I)) & 1u;
+    else return true;
+  };
+  auto nrow = [&](auto I) __attribute__((always_inline)) -> int64_t {
+    return int64_t(__builtin_amdgcn_readlane(rk_lane, CV(I)));
+  };
 
   // LDS-DMA prefetch of one tile of the backward sweep
   auto prefetch = [&](int it) __attribute__((always_inline)) {
@@ -917,7 +932,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((
                           reinterpret_cast<const char *>(A.dphi)};
     static_for<0, 4>([&](auto S) __attribute__((always_inline)) {
       constexpr int sl = CV(S);
-      if constexpr ((PFMASK >> sl) & 1) {
+      if constexpr (((PFMASK >> sl) & 1) && NUM) {
+        // sector rows of the current item; rows outside the sector are not
+        // loaded (zeroed in LDS once the loads have landed)
+        constexpr int li = __builtin_popcount(PFMASK & ((1 << sl) - 1));
+        if constexpr (DW == 2) {
+          const uint32_t hoff = uint32_t(lane & 31) * 16;
+          const int64_t colb = int64_t(pcg) * 64 * ES;
+          static_for<0, NA / 2>([&](auto I2) __attribute__((always_inline)) {
+            constexpr int i0 = 2 * CV(I2);
+            const bool v0 = rvalid(ic<i0>{}), v1 = rvalid(ic<i0 + 1>{});
+            const int64_t r0 = nrow(ic<i0>{}), r1 = nrow(ic<i0 + 1>{});
+            const int64_t rb = ((lane < 32) ? r0 : r1) * A.ld * ES;
+            if ((lane < 32) ? v0 : v1)
+              lds_dma<16>(src[sl] + rb + colb + hoff, pf + (li * NA + i0) * 64 * int(ES));
+          });
+        } else {
+          static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+            if (rvalid(I))
+              lds_dma<16>(src[sl] + nrow(I) * A.ld * ES + pvoff,
+                          pf + (li * NA + CV(I)) * 64 * int(ES));
+          });
+        }
+      } else if constexpr ((PFMASK >> sl) & 1) {
         constexpr int li = __builtin_popcount(PFMASK & ((1 << sl) - 1));
         if constexpr (DW == 2) {
           // complex64: 16 bytes per lane = two columns; lanes 0-31 fetch row
@@ -951,7 +988,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((
       return reinterpret_cast<const cx<R> *>(l)[lane];
     } else {
       const void *base = sl == 0 ? A.ckpt_psi : sl == 1 ? A.phi : sl == 2 ? A.ckpt_dpsi : A.dphi;
-      return ldrow<R>(reinterpret_cast<const char *>(base) + rowb + boff(I), voff);
+      if constexpr (NUM) {
+        cx<R> v{R(0), R(0)};
+        if (rvalid(I)) v = ldrow<R>(reinterpret_cast<const char *>(base) + nrow(I) * A.ld * ES, voff);
+        return v;
+      } else {
+        return ldrow<R>(reinterpret_cast<const char *>(base) + rowb + boff(I), voff);
+      }
     }
   };
   if constexpr (PF && !LRES) {
@@ -976,17 +1019,52 @@ __global__ __launch_bounds__(kBlock) __attribute__((
           t >>= 1;
         }
     }
-    const int pi = MODE == MODE_PARITY ? ((A.sector ^ __builtin_popcountll(base)) & 1) : 0;
+    // implied bit of local amplitude i: sector ^ parity(base) ^ parity(i); in
+    // a particle-number sector it is M - popcount(i), M = n - popcount(base),
+    // which has the same parity, so both modes share the gate cases
+    const int pi = MODE != MODE_DENSE ? ((A.sector ^ __builtin_popcountll(base)) & 1) : 0;
+    if constexpr (NUM) {
+      // basis index of local amplitude i: row bits base | lrow(i), then the
+      // implied bit M - popcount(i) (0 or 1 inside the sector)
+      const int M = A.sector - __builtin_popcountll(base);
+      if (M < 0 || M > NT + 1) continue;  // no state of the sector on this tile
+      bool vl = false;
+      rk_lane = 0;
+      if (lane < NA) {
+        int64_t lr = 0;
+        for (int b = 0; b < NT; ++b)
+          if ((lane >> b) & 1) lr |= int64_t(1) << A.pos[b];
+        const int imp = M - __builtin_popcount(lane);
+        vl = imp == 0 || imp == 1;
+        if (vl) rk_lane = A.rank[((base | lr) << 1) | imp];
+      }
+      vmask = uint32_t(__builtin_amdgcn_ballot_w64(vl));
+    }
     const int64_t rowb = base * A.ld * ES;        // byte offset of the tile's first row
     const cx<R> zero{R(0), R(0)};
 
     cx<R> ps[NA], dps[NA], ph[NA], dph[NA];
     if constexpr (NEEDF) {
-      if (A.src_psi) {
+      if (A.src_psi && NUM) {
+        const char *s = reinterpret_cast<const char *>(A.src_psi);
+        static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+          ps[CV(I)] = zero;
+          if (rvalid(I)) {
+            const cx<R> v = ldrow<R>(s + nrow(I) * A.ld_src * ES, voff);
+            ps[CV(I)] = ok ? v : zero;
+          }
+        });
+      } else if (A.src_psi) {
         const char *s = reinterpret_cast<const char *>(A.src_psi) + base * A.ld_src * ES;
         static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
           const cx<R> v = ldrow<R>(s + soff(I), voff);
           ps[CV(I)] = ok ? v : zero;
+        });
+      } else if constexpr (NUM) {
+        const int64_t tgt = A.col0 + c;
+        static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+          ps[CV(I)].x = (ok && rvalid(I) && nrow(I) == tgt) ? R(1) : R(0);
+          ps[CV(I)].y = R(0);
         });
       } else {
         const int64_t tgt = A.col0 + c - base;
@@ -996,7 +1074,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((
         });
       }
       if constexpr (HV) {
-        if (A.src_dpsi) {
+        if (A.src_dpsi && NUM) {
+          const char *s = reinterpret_cast<const char *>(A.src_dpsi);
+          static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+            dps[CV(I)] = zero;
+            if (rvalid(I)) {
+              const cx<R> v = ldrow<R>(s + nrow(I) * A.ld * ES, voff);
+              dps[CV(I)] = ok ? v : zero;
+            }
+          });
+        } else if (A.src_dpsi) {
           const char *s = reinterpret_cast<const char *>(A.src_dpsi) + rowb;
           static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
             const cx<R> v = ldrow<R>(s + boff(I), voff);
@@ -1013,7 +1100,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((
           fwd_gate<R, NT, MODE, HV, CV(CC)>(ps, dps, co);
         });
       }
-      if constexpr (STAGE == ST_FWD) {
+      if constexpr (STAGE == ST_FWD && NUM) {
+        if (ok) {
+          static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+            if (rvalid(I)) {
+              const int64_t o = nrow(I) * A.ld * ES;
+              strow<R>(reinterpret_cast<char *>(A.dst_psi) + o, voff, ps[CV(I)]);
+              if constexpr (HV) strow<R>(reinterpret_cast<char *>(A.dst_dpsi) + o, voff, dps[CV(I)]);
+            }
+          });
+        }
+      } else if constexpr (STAGE == ST_FWD) {
         if (ok) {
           char *d = reinterpret_cast<char *>(A.dst_psi) + rowb;
           static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
@@ -1039,6 +1136,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((
         if constexpr (HV) dph[CV(I)] = pf_read(ic<3>{}, I, rowb, voff);
       });
       wait_vmcnt<0>();
+      if constexpr (NUM) {  // amplitudes outside the sector: zero, not loaded
+        static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+          if (!rvalid(I)) {
+            sps[CV(I) * 64 + lane] = zero;
+            if constexpr (HV) sdps[CV(I) * 64 + lane] = zero;
+          }
+        });
+      }
       if (!ok) {  // padding columns of a ragged chunk: zero states
         static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
           sps[CV(I) * 64 + lane] = zero;
@@ -1077,12 +1182,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((
 
     if constexpr (STAGE == ST_LAST) {
       // phi_0 = conj(U|j>), overlap h_j = sum_x phi_0[x] psi_N[x]
-      const char *u = reinterpret_cast<const char *>(A.ref) + base * A.ld_ref * ES +
+      const char *u = reinterpret_cast<const char *>(A.ref) + (NUM ? 0 : base * A.ld_ref * ES) +
                       A.col0 * int64_t(ES);
       R hre = R(0);
       static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
         constexpr int i = CV(I);
-        const cx<R> v = ldrow<R>(u + roff(I), voff);
+        cx<R> v = zero;
+        if constexpr (NUM) {
+          if (rvalid(I)) v = ldrow<R>(u + nrow(I) * A.ld_ref * ES, voff);
+        } else {
+          v = ldrow<R>(u + roff(I), voff);
+        }
         ph[i].x = ok ? v.x : R(0);
         ph[i].y = ok ? -v.y : R(0);
         hre = fma(ph[i].x, ps[i].x, hre);
@@ -1117,7 +1227,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((
         const double r = wave_reduce_scatter<R, NE>(tp, lane);
         if (writer) acc[g * NE + my_e] += r;
       }
-      if (A.store_phi && ok) {
+      if (A.store_phi && ok && NUM) {
+        static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+          if (rvalid(I)) {
+            const int64_t o = nrow(I) * A.ld * ES;
+            strow<R>(reinterpret_cast<char *>(A.phi) + o, voff, ph[CV(I)]);
+            if constexpr (HV) strow<R>(reinterpret_cast<char *>(A.dphi) + o, voff, dph[CV(I)]);
+          }
+        });
+      } else if (A.store_phi && ok) {
         char *p = reinterpret_cast<char *>(A.phi) + rowb;
         static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
           strow<R>(p + boff(I), voff, ph[CV(I)]);
@@ -1208,7 +1326,9 @@ template <typename R, int NT, bool COST, bool GRAD, bool HVPD, bool HVPP>
 static int launch_nt(int mode, int op, int stage, const PassArgs &a, int grid, void *s) {
   return mode == MODE_DENSE
              ? launch_mode<R, NT, MODE_DENSE, COST, GRAD, HVPD>(op, stage, a, grid, s)
-             : launch_mode<R, NT, MODE_PARITY, COST, GRAD, HVPP>(op, stage, a, grid, s);
+         : mode == MODE_PARITY
+             ? launch_mode<R, NT, MODE_PARITY, COST, GRAD, HVPP>(op, stage, a, grid, s)
+             : launch_mode<R, NT, MODE_NUMBER, COST, GRAD, HVPP>(op, stage, a, grid, s);
 }
 
 }  // namespace rqk

@@ -14,6 +14,7 @@ basis index; in parity mode states are sector-compressed (row x >> 1).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
@@ -28,6 +29,7 @@ RQ_OK, RQ_EINVAL, RQ_EHIP, RQ_ESPACE, RQ_ESINGULAR = 0, 1, 2, 3, 4
 RQ_C128, RQ_C64 = 0, 1
 RQ_PARITY = 1
 RQ_NUMBER = 2
+RQ_SECTORS = 4
 RQ_OP_COST, RQ_OP_GRAD, RQ_OP_HVP, RQ_OP_HESS, RQ_OP_APPLY = 0, 1, 2, 3, 4
 
 
@@ -64,7 +66,7 @@ EXPORTS = ["rq_workspace_bytes", "rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks
            "rq_tangent_coords", "rq_tr_workspace_bytes", "rq_tr_solve",
            "rq_tangent_basis", "rq_plan_passes", "rq_profile_enable", "rq_profile_read",
            "rq_stream_copy", "rq_hvp_static", "rq_orbit_reps", "rq_orbit_workspace_bytes",
-           "rq_orbit_target", "rq_strerror", "rq_last_error"]
+           "rq_orbit_target", "rq_sector_rows", "rq_strerror", "rq_last_error"]
 
 
 def lib():
@@ -112,9 +114,10 @@ def lib():
                                   C.POINTER(_Exec)]
     L.rq_hvp_static.argtypes = common + [dp, C.POINTER(_Range), P, C.c_uint32,
                                          C.POINTER(C.c_int64), P, P, P, P, P]
+    L.rq_sector_rows.argtypes = [C.c_int32, C.POINTER(C.c_int64)]
     L.rq_strerror.restype = C.c_char_p
     L.rq_last_error.restype = C.c_char_p
-    for name in ["rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks", "rq_apply_circuit",
+    for name in ["rq_sector_rows", "rq_cost", "rq_grad", "rq_hvp", "rq_hess_blocks", "rq_apply_circuit",
                  "rq_tr_step", "rq_tr_accept", "rq_tangent_basis", "rq_plan_passes",
                  "rq_tangent_coords", "rq_tr_solve", "rq_stream_copy", "rq_hvp_static",
                  "rq_orbit_reps", "rq_orbit_target",
@@ -155,7 +158,8 @@ class Circuit:
     """Gate topology: k qubits, pairs [(q_hi, q_lo)], optional param_of."""
 
     def __init__(self, k: int, pairs: Sequence, param_of=None, n_params: Optional[int] = None,
-                 parity: bool = False, shift: int = 0, number: bool = False):
+                 parity: bool = False, shift: int = 0, number: bool = False,
+                 sectors: bool = False):
         self.k = int(k)
         self.pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
         self.n_gates = self.pairs.shape[0]
@@ -167,8 +171,11 @@ class Circuit:
             self.n_params = int(self.param_of.max()) + 1 if n_params is None else int(n_params)
         self.parity = bool(parity) or bool(number)
         self.number = bool(number)      # particle-number-conserving gates (implies parity)
+        # states stored per particle-number sector (requires number)
+        self.sectors = bool(sectors)
         self.shift = int(shift)   # translation symmetry (qubits), 0: none
-        self.flags = (RQ_PARITY if self.parity else 0) | (RQ_NUMBER if self.number else 0)
+        self.flags = (RQ_PARITY if self.parity else 0) | (RQ_NUMBER if self.number else 0) | \
+            (RQ_SECTORS if self.sectors else 0)
         self._c = _Circuit(self.k, self.n_gates, self.n_params, self.flags,
                            self.pairs.ctypes.data_as(C.POINTER(C.c_int32)),
                            None if self.param_of is None
@@ -181,6 +188,10 @@ class Circuit:
 
     @property
     def ncols(self):
+        """Basis columns of the largest sector (parity: 2^(k-1); particle
+        number: C(k, k // 2); general: 2^k)."""
+        if self.sectors:
+            return math.comb(self.k, self.k // 2)
         return 1 << self.kq
 
     def plan(self, op: int, dtype: int):
@@ -205,6 +216,22 @@ def sector_rows(k: int, p: int) -> np.ndarray:
         par ^= v & 1
         v >>= 1
     return (xp << 1) | (par ^ p)
+
+
+def sector_order(k: int) -> np.ndarray:
+    """Stacked particle-number-sector row of every basis index x < 2^k
+    (rq_sector_rows): sectors by particle number, states of a sector in
+    increasing order."""
+    rows = np.zeros(1 << k, dtype=np.int64)
+    _check(lib().rq_sector_rows(k, rows.ctypes.data_as(C.POINTER(C.c_int64))), "rq_sector_rows")
+    return rows
+
+
+def sector_bounds(k: int):
+    """[(first stacked row, size)] of the particle-number sectors n = 0..k."""
+    sizes = [math.comb(k, n) for n in range(k + 1)]
+    first = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    return [(int(f), int(d)) for f, d in zip(first, sizes)]
 
 
 @dataclass
@@ -245,6 +272,22 @@ class Target:
         ild, iss = self._geometry(self.inputs, self.parity)
         return _Target(self.dtype, 0, ref, ld, ss,
                        self.inputs.data_ptr() - self.col_offset * esize, ild, iss)
+
+    @staticmethod
+    def from_dense_sectors(U: np.ndarray, dtype: int = RQ_C128, device="cuda"):
+        """Particle-number-sector target (RQ_SECTORS) from a dense U that
+        conserves particle number: [2^k, C(k, k//2)] with the block of sector
+        n at rows [first(n), first(n) + C(k, n)), columns [0, C(k, n))."""
+        U = np.asarray(U)
+        k = int(np.log2(U.shape[0]))
+        order = np.argsort(sector_order(k))          # stacked row -> basis index
+        width = math.comb(k, k // 2)
+        ref = np.zeros((1 << k, width), dtype=np.complex128)
+        for first, size in sector_bounds(k):
+            idx = order[first:first + size]
+            ref[first:first + size, :size] = U[np.ix_(idx, idx)]
+        t = torch.from_numpy(ref).to(torch_dtype(dtype))
+        return Target(t.to(device), dtype, False)
 
     @staticmethod
     def from_dense(U: np.ndarray, dtype: int = RQ_C128, parity: bool = False, device="cuda"):
@@ -563,11 +606,12 @@ def rq_tr_solve(circuit: Circuit, target: Target, gates, max_iter: int = 20, gto
     return G, hist[:n.value]
 
 
-def apply_workspace(k: int, gate_list, dtype: int, parity: bool = False) -> Workspace:
+def apply_workspace(k: int, gate_list, dtype: int, parity: bool = False,
+                    sectors: bool = False) -> Workspace:
     """Workspace for rq_apply_circuit with a gate list (its gate
     coefficients), for callers that run several applications concurrently on
     different streams and must not share one."""
-    circ = Circuit(k, [p for p, _ in gate_list], parity=parity)
+    circ = Circuit(k, [p for p, _ in gate_list], parity=parity, number=sectors, sectors=sectors)
     need = lib().rq_workspace_bytes(C.byref(circ._c), RQ_OP_APPLY, dtype, 0)
     if need == 0:
         raise RQError(RQ_EINVAL, "rq_workspace_bytes")
@@ -575,7 +619,8 @@ def apply_workspace(k: int, gate_list, dtype: int, parity: bool = False) -> Work
 
 
 def build_trotter_target(k: int, gate_list, dtype: int = RQ_C128, parity: bool = True,
-                         device="cuda", workspace=None, stream=None) -> Target:
+                         device="cuda", workspace=None, stream=None,
+                         sectors: bool = False) -> Target:
     """Target columns U|j> for every basis state, built on the device by
     applying a gate list (e.g. a Trotter circuit) to the identity columns with
     rq_apply_circuit.  Parity mode returns the two sector blocks.  The work is
@@ -583,10 +628,20 @@ def build_trotter_target(k: int, gate_list, dtype: int = RQ_C128, parity: bool =
     (default: the stream's cached apply workspace)."""
     pairs = [p for p, _ in gate_list]
     gates = np.stack([G for _, G in gate_list])
-    circ = Circuit(k, pairs, parity=parity)
+    circ = Circuit(k, pairs, parity=parity, number=sectors, sectors=sectors)
     td = torch_dtype(dtype)
     s = stream if stream is not None else torch.cuda.current_stream()
     with torch.cuda.stream(s):
+        if sectors:
+            # particle-number sectors (the gate list must conserve particle
+            # number): the identity block of every sector, then the circuit
+            ref = torch.zeros((1 << k, math.comb(k, k // 2)), dtype=td, device=device)
+            for n, (first, size) in enumerate(sector_bounds(k)):
+                blk = ref[first:first + size, :size]
+                blk.fill_diagonal_(1.0)
+                rq_apply_circuit(circ, gates, blk, dtype=dtype, sector=n, workspace=workspace,
+                                 stream=s)
+            return Target(ref, dtype, False)
         if parity:
             n = 1 << (k - 1)
             ref = torch.zeros((2, n, n), dtype=td, device=device)
