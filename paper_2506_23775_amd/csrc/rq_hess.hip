@@ -133,10 +133,24 @@ __device__ __forceinline__ void slice_entry(int mode, int nd, int mu, int &a, in
   }
 }
 
+// Target wavefronts per SIMD of the hole-array sweep: three for complex64
+// parity gates on 5-qubit tiles in blocks of four (the compiler's own
+// allocation takes 177 registers, 9 more than three wavefronts leave; at
+// 168 it spills 44 bytes per lane and runs the configuration-3 sweep 4 %
+// faster), otherwise the compiler's own allocation (the three-wavefront
+// blocks of particle-number gates would spill 124 bytes and run 23 %
+// slower).
+template <typename R, int NT, int MODE, int W>
+struct HessWaves {
+  static constexpr int value =
+      (sizeof(R) == 4 && NT == 5 && MODE == MODE_PARITY && W == 4) ? 3 : 1;
+};
+
 // W wavefronts per block, one slice each: 4, or 3 for the six slices of
 // particle-number gates (two blocks per item, no idle wavefronts).
 template <typename R, int NT, int MODE, int W>
-__global__ __launch_bounds__(kBlock) void k_hess_pass(const HessArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    HessWaves<R, NT, MODE, W>::value))) void k_hess_pass(const HessArgs A) {
   constexpr int NA = 1 << NT;
   constexpr int NE = MODE == MODE_DENSE ? 32 : 16;
   constexpr int LV = ilog2<NE>();
