@@ -1068,8 +1068,11 @@ int run_hess(const rq_circuit *c, const rq_target *t, const double *gates, const
       const int resident = launch_hess_pass(L.is_double, H.nt, L.parity, ha, -1, s);
       if (resident <= 0) return fail(RQ_EHIP, "Hessian sweep occupancy query failed");
       const int64_t blocks = std::min<int64_t>(resident, kHessSlots / wpb);
-      const int gridh =
+      int gridh =
           ha.nquads * (int)std::max<int64_t>(1, std::min<int64_t>(ha.n_rest, blocks / ha.nquads));
+      // a multiple of 8 * nquads blocks lets the kernel give the nquads
+      // blocks of an item to one XCD (see k_hess_pass)
+      if (gridh >= kXcds * ha.nquads) gridh -= gridh % (kXcds * ha.nquads);
       const int rows_all = N * H.nd * H.ne;
       for (int t = 0; t + 1 < N; ++t) {
         const int h = order[t];

@@ -172,10 +172,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   const int my_e = entry_of_lane(lane, LV);
   const bool writer = entry_writer(lane, LV);
   // block -> (slice group, first item); the W wavefronts of a block take
-  // four consecutive slices of the same items
-  const int quad = blockIdx.x % A.nquads;
-  const int rest0 = blockIdx.x / A.nquads;
-  const int rstride = gridDim.x / A.nquads;
+  // W consecutive slices of the same items.  Consecutive blocks go to the
+  // XCDs in turn, so when the grid is a multiple of kXcds * nquads the
+  // nquads blocks of an item are blocks b, b + kXcds, ... of one XCD,
+  // started together: the second and later reads of each phi tile hit that
+  // XCD's L2 instead of HBM.  Otherwise consecutive blocks share an item.
+  const int nq = A.nquads;
+  const bool xcd = gridDim.x % (kXcds * nq) == 0;
+  const int quad = xcd ? (blockIdx.x / kXcds) % nq : blockIdx.x % nq;
+  const int rest0 = xcd ? (blockIdx.x / (kXcds * nq)) * kXcds + blockIdx.x % kXcds
+                        : blockIdx.x / nq;
+  const int rstride = gridDim.x / nq;
   const int mu = quad * W + wib;
   const bool active = mu < A.nd;           // particle-number mode pads 6 slices to 8
   int ea = 0, eb = 0;

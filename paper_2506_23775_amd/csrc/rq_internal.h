@@ -113,6 +113,9 @@ struct StateArgs {
 // FP64 partial-sum slots (one per wavefront) of the Hessian sweeps: four
 // wavefronts per SIMD of 256 compute units.
 constexpr int kHessSlots = 4096;
+// Accelerator complex dies (XCDs, each with its own L2) over which the
+// hardware deals consecutive workgroups of a launch in turn.
+constexpr int kXcds = 8;
 
 // Host-side launchers (defined in rq_launch.hip, rq_hess.hip and the sweep
 // instantiation units).
