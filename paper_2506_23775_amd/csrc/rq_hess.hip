@@ -134,20 +134,20 @@ __device__ __forceinline__ void slice_entry(int mode, int nd, int mu, int &a, in
 }
 
 // Target wavefronts per SIMD of the hole-array sweep: three for complex64
-// parity gates on 5-qubit tiles in blocks of four (the compiler's own
-// allocation takes 177 registers, 9 more than three wavefronts leave; at
-// 168 it spills 44 bytes per lane and runs the configuration-3 sweep 4 %
-// faster), otherwise the compiler's own allocation (the three-wavefront
-// blocks of particle-number gates would spill 124 bytes and run 23 %
-// slower).
+// parity gates on 5-qubit tiles (the compiler's own allocation takes 177
+// registers, 9 more than three wavefronts leave; at 168 it spills 44 bytes
+// per lane and runs the configuration-3 sweep 4 % faster), otherwise the
+// compiler's own allocation.
 template <typename R, int NT, int MODE, int W>
 struct HessWaves {
   static constexpr int value =
       (sizeof(R) == 4 && NT == 5 && MODE == MODE_PARITY && W == 4) ? 3 : 1;
 };
 
-// W wavefronts per block, one slice each: 4, or 3 for the six slices of
-// particle-number gates (two blocks per item, no idle wavefronts).
+// W wavefronts per block, one slice each (W = 4: the six slices of
+// particle-number gates leave two wavefronts of an item's second block
+// idle, which at three wavefronts per SIMD runs faster than blocks of three
+// at two).
 template <typename R, int NT, int MODE, int W>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     HessWaves<R, NT, MODE, W>::value))) void k_hess_pass(const HessArgs A) {
@@ -610,14 +610,11 @@ static int launch_hess_w(const HessArgs &a, int grid, void *s) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// wavefronts per block: 3 for the 6 slices of particle-number gates, else 4
-int hess_block_waves(int nd) { return nd == 6 ? 3 : 4; }
+// wavefronts per block of the hole-array sweep (any number of slices)
+int hess_block_waves(int) { return 4; }
 
 template <typename R, int NT, int MODE>
 static int launch_hess_one(const HessArgs &a, int grid, void *s) {
-  if constexpr (MODE == MODE_PARITY) {
-    if (a.nd == 6) return launch_hess_w<R, NT, MODE, 3>(a, grid, s);
-  }
   return launch_hess_w<R, NT, MODE, 4>(a, grid, s);
 }
 
