@@ -418,6 +418,8 @@ def main():
                     help="1: time the translation-orbit-reduced evaluation (0: skip)")
     ap.add_argument("--hessian", type=int, default=1,
                     help="1: time the configuration-3 Hessian blocks (0: skip)")
+    ap.add_argument("--hessian-c128", type=int, default=1,
+                    help="1: also the configuration-3 Hessian with complex128 states (0: skip)")
     ap.add_argument("--hessian-number", type=int, default=1,
                     help="1: also the Hessian with particle-number-conserving gates (0: skip)")
     ap.add_argument("--tr-iters", type=int, default=5,
@@ -524,6 +526,35 @@ def main():
             "symmetric_rel": float(f"{np.abs(hr - hr.T).max() / np.abs(hr).max():.2e}")}
         out["hessian"]["roofline"]["traffic"] = measured_traffic("cfg3:hess/sweep", "hess")
         log(f"[bench] Hessian: {dt:.2f} s")
+        if args.hessian_c128 and tgt128 is not None:
+            # the same Hessian with complex128 states (the paper's precision),
+            # and the complex64 Hessian's deviation from it
+            log("[bench] Hessian leg: configuration 3, complex128")
+            rq.release_workspaces()
+            torch.cuda.synchronize()
+            rq.rq_profile_read()
+            rq.rq_profile_enable(True)
+            t0 = time.perf_counter()
+            h128 = rq.rq_hess_blocks(c3s, tgt128, prob.gates, chunk=1024)
+            torch.cuda.synchronize()
+            dt128 = time.perf_counter() - t0
+            rq.rq_profile_enable(False)
+            hprof128 = rq.rq_profile_read()
+            hr128 = h128[4].cpu().numpy()
+            hh64, hh128 = hres[3].cpu().numpy(), h128[3].cpu().numpy()
+            out["hessian_c128"] = {
+                "workload": "the cfg3 Hessian leg with complex128 states (FP64 throughout)",
+                "seconds": round(dt128, 3),
+                "sweep_ms": round(hprof128[("hess", "sweep")]["ms"], 1),
+                "sweep_launches": hprof128[("hess", "sweep")]["launches"],
+                "roofline": roofline(hprof128, ("hess", "sweep")),
+                "c64_rel_error": {
+                    "hess_real": float(f"{np.linalg.norm(hr - hr128) / np.linalg.norm(hr128):.3e}"),
+                    "hess_holo": float(f"{np.linalg.norm(hh64 - hh128) / np.linalg.norm(hh128):.3e}")}}
+            del h128
+            rq.release_workspaces()
+            torch.cuda.empty_cache()
+            log(f"[bench] Hessian (c128): {dt128:.2f} s")
     if args.hessian and args.hessian_number:
         # the same Hessian with particle-number-conserving gates (6 hole
         # slices instead of 8)
