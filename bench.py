@@ -154,7 +154,7 @@ def code_hash(path):
 # code hash keys the measurement)
 TRAFFIC_PROFILES = {
     "sweep": ("k_pass_hvp_cfg3_c64.txt", "rq_sweep.h"),
-    "hess": ("k_hess_pass_cfg3_cfg4_c64.txt", "rq_hess.hip"),
+    "hess": ("k_hess_pass_cfg3_cfg4.txt", "rq_hess.hip"),
     "cfg4": ("k_pass_hvp_cfg4_c64.txt", "rq_sweep.h"),
 }
 
@@ -547,7 +547,8 @@ def main():
                 "seconds": round(dt128, 3),
                 "sweep_ms": round(hprof128[("hess", "sweep")]["ms"], 1),
                 "sweep_launches": hprof128[("hess", "sweep")]["launches"],
-                "roofline": roofline(hprof128, ("hess", "sweep")),
+                "roofline": dict(roofline(hprof128, ("hess", "sweep")),
+                                 traffic=measured_traffic("cfg3c128:hess/sweep", "hess")),
                 "c64_rel_error": {
                     "hess_real": float(f"{np.linalg.norm(hr - hr128) / np.linalg.norm(hr128):.3e}"),
                     "hess_holo": float(f"{np.linalg.norm(hh64 - hh128) / np.linalg.norm(hh128):.3e}")}}
