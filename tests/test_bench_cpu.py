@@ -38,6 +38,14 @@ def test_measured_traffic_lookup():
         # otherwise at least the 6 GiB the pass must move (4 slabs read, 2
         # written, 1 GiB each at the benchmark's chunk)
         assert v is None or v >= 0.9 * 6 * 2**30, (key, v)
+    # Hessian sweeps (keyed on the Hessian kernel source): at least the
+    # slices written per launch (8 slices x 2^15 rows x 1024 columns: 2 GiB
+    # in complex64, 4 GiB in complex128; configuration 4: 16 slices x 2^16
+    # rows, 8 GiB)
+    for key, least in (("cfg3:hess/sweep", 2 * 2**30), ("cfg3c128:hess/sweep", 4 * 2**30),
+                       ("cfg4:hess/sweep", 8 * 2**30)):
+        v = bench.measured_traffic(key, "hess")
+        assert v is None or v >= 0.99 * least, (key, v)
 
 
 def test_cpu_baseline_batches_over_workers():
