@@ -575,6 +575,7 @@ def main():
                         "6 x 6 blocks, 6 hole slices), same target and symmetry",
             "seconds": round(dtn, 3),
             "sweep_ms": round(nprof[("hess", "sweep")]["ms"], 1),
+            "roofline": roofline(nprof, ("hess", "sweep")),
             "speedup_vs_parity_gates": round(out["hessian"]["seconds"] / dtn, 3)}
         log(f"[bench] Hessian (number gates): {dtn:.2f} s")
 
