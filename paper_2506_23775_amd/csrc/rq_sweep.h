@@ -79,6 +79,15 @@ __device__ __forceinline__ void cfma(cx<R> &y, cx<R> c, cx<R> x) {
   y.y = fma(c.y, x.x, y.y);
 }
 
+// y -= c x (fused: no separate product and subtraction)
+template <typename R>
+__device__ __forceinline__ void cfms(cx<R> &y, cx<R> c, cx<R> x) {
+  y.x = fma(-c.x, x.x, y.x);
+  y.x = fma(c.y, x.y, y.x);
+  y.y = fma(-c.x, x.y, y.y);
+  y.y = fma(-c.y, x.x, y.y);
+}
+
 // (re, im) += a b
 template <typename R>
 __device__ __forceinline__ void cacc(R &re, R &im, cx<R> a, cx<R> b) {
@@ -349,11 +358,9 @@ __device__ __forceinline__ void bwd_gate(cx<R> (&ps)[NA], cx<R> (&dps)[NA], cx<R
             cx<R> y = mv2(gi[4 * a], dps[id[0]], gi[4 * a + 1], dps[id[1]]);
             cfma(y, gi[4 * a + 2], dps[id[2]]);
             cfma(y, gi[4 * a + 3], dps[id[3]]);
-            cx<R> m = mv2(giz[4 * a], x[0], giz[4 * a + 1], x[1]);
-            cfma(m, giz[4 * a + 2], x[2]);
-            cfma(m, giz[4 * a + 3], x[3]);
-            y.x -= m.x;
-            y.y -= m.y;
+            static_for<0, 4>([&](auto B) __attribute__((always_inline)) {
+              cfms(y, giz[4 * a + CV(B)], x[CV(B)]);
+            });
             xd[a] = y;
             pd[a] = dph[id[a]];
           });
@@ -411,12 +418,10 @@ __device__ __forceinline__ void bwd_gate(cx<R> (&ps)[NA], cx<R> (&dps)[NA], cx<R
         if constexpr (HV) {
           cx<R> xd0 = mv2(gi[c00], dps[i0], gi[c01], dps[i1]);
           cx<R> xd1 = mv2(gi[c10], dps[i0], gi[c11], dps[i1]);
-          const cx<R> m0 = mv2(giz[c00], x0, giz[c01], x1);
-          const cx<R> m1 = mv2(giz[c10], x0, giz[c11], x1);
-          xd0.x -= m0.x;
-          xd0.y -= m0.y;
-          xd1.x -= m1.x;
-          xd1.y -= m1.y;
+          cfms(xd0, giz[c00], x0);
+          cfms(xd0, giz[c01], x1);
+          cfms(xd1, giz[c10], x0);
+          cfms(xd1, giz[c11], x1);
           const cx<R> q0 = dph[i0], q1 = dph[i1];
           cacc(tp[TD + 2 * c00], tp[TD + 2 * c00 + 1], q0, x0);
           cacc(tp[TD + 2 * c01], tp[TD + 2 * c01 + 1], q0, x1);
@@ -489,11 +494,9 @@ __device__ __forceinline__ void bwd_gate_l(cx<R> *sps, cx<R> *sdps, int lane, cx
               cx<R> y = mv2(gi[4 * a], d[0], gi[4 * a + 1], d[1]);
               cfma(y, gi[4 * a + 2], d[2]);
               cfma(y, gi[4 * a + 3], d[3]);
-              cx<R> m = mv2(giz[4 * a], x[0], giz[4 * a + 1], x[1]);
-              cfma(m, giz[4 * a + 2], x[2]);
-              cfma(m, giz[4 * a + 3], x[3]);
-              y.x -= m.x;
-              y.y -= m.y;
+              static_for<0, 4>([&](auto B) __attribute__((always_inline)) {
+                cfms(y, giz[4 * a + CV(B)], x[CV(B)]);
+              });
               dps(id[a]) = y;
             });
           }
@@ -576,12 +579,10 @@ __device__ __forceinline__ void bwd_gate_l(cx<R> *sps, cx<R> *sdps, int lane, cx
         if constexpr (HV) {
           cx<R> xd0 = mv2(gi[c00], dps(i0), gi[c01], dps(i1));
           cx<R> xd1 = mv2(gi[c10], dps(i0), gi[c11], dps(i1));
-          const cx<R> m0 = mv2(giz[c00], x0, giz[c01], x1);
-          const cx<R> m1 = mv2(giz[c10], x0, giz[c11], x1);
-          xd0.x -= m0.x;
-          xd0.y -= m0.y;
-          xd1.x -= m1.x;
-          xd1.y -= m1.y;
+          cfms(xd0, giz[c00], x0);
+          cfms(xd0, giz[c01], x1);
+          cfms(xd1, giz[c10], x0);
+          cfms(xd1, giz[c11], x1);
           const cx<R> q0 = dph[i0], q1 = dph[i1];
           cacc(tp[TD + 2 * c00], tp[TD + 2 * c00 + 1], q0, x0);
           cacc(tp[TD + 2 * c01], tp[TD + 2 * c01 + 1], q0, x1);
