@@ -575,7 +575,9 @@ def main():
                         "6 x 6 blocks, 6 hole slices), same target and symmetry",
             "seconds": round(dtn, 3),
             "sweep_ms": round(nprof[("hess", "sweep")]["ms"], 1),
-            "roofline": roofline(nprof, ("hess", "sweep")),
+            "sweep_launches": nprof[("hess", "sweep")]["launches"],
+            "roofline": dict(roofline(nprof, ("hess", "sweep")),
+                             traffic=measured_traffic("cfg3num:hess/sweep", "hess")),
             "speedup_vs_parity_gates": round(out["hessian"]["seconds"] / dtn, 3)}
         log(f"[bench] Hessian (number gates): {dtn:.2f} s")
 

@@ -250,11 +250,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     char *sl = reinterpret_cast<char *>(A.psi) + int64_t(active ? mu : 0) * A.slab * ES + rowb;
     const char *ld_src = A.hole_src ? reinterpret_cast<const char *>(A.hole_src) + rowb : sl;
     cx<R> ps[NA];
-    static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
-      const cx<R> v = ldrow<R>(ld_src + boff(I), voff);
-      ps[CV(I)] = ok ? v : zero;
-    });
-    if (A.hole_src) {
+    // a padding wavefront (no slice: particle-number gates have 6 of 8)
+    // reads nothing and computes nothing; it only takes its share of the
+    // phi loads and the barriers of its block
+    if (active) {
+      static_for<0, NA>([&](auto I) __attribute__((always_inline)) {
+        const cx<R> v = ldrow<R>(ld_src + boff(I), voff);
+        ps[CV(I)] = ok ? v : zero;
+      });
+    } else {
+      static_for<0, NA>([&](auto I) __attribute__((always_inline)) { ps[CV(I)] = zero; });
+    }
+    if (A.hole_src && active) {
       const GateRef gr = A.gates[0];
       dispatch<0, K::n>(gate_code(MODE, NT, gr, pi), [&](auto CC) __attribute__((always_inline)) {
         hole_slice<R, NT, MODE, CV(CC)>(ps, ea, eb);
@@ -263,8 +270,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     for (int g = g0; g < A.ngates; ++g) {
       // this gate's phi tile is in LDS buffer `buf` once every wavefront's
       // loads completed: only this item's slice loads (NA vector-memory
-      // instructions) were issued after it in the first gate, none later
-      if (g == g0)
+      // instructions) were issued after it in the first gate, none later,
+      // and none at all by a padding wavefront
+      if (g == g0 && active)
         wait_vmcnt<NA>();
       else
         wait_vmcnt<0>();
@@ -276,18 +284,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
       else if (rest + rstride < A.n_rest)
         prefetch(rest + rstride, g0, buf ^ 1);
       asm volatile("" ::: "memory");
-      const GateRef gr = A.gates[g];
-      ccoef_t<R> *co = coef + int64_t(gr.inst) * kCoefStride;
-      const cx<R> *ph = phb + buf * NA * 64 + lane;
-      R tp[NE];
-      // -0: the first fma into each partial folds into a multiply
-      static_for<0, NE>([&](auto E) __attribute__((always_inline)) { tp[CV(E)] = R(-0.0); });
-      dispatch<0, K::n>(gate_code(MODE, NT, gr, pi), [&](auto CC) __attribute__((always_inline)) {
-        contract_gate<R, NT, MODE, CV(CC), NE>(ps, ph, tp);
-        fwd_gate<R, NT, MODE, false, CV(CC)>(ps, ps, co);
-      });
-      const double r = wave_reduce_scatter<R, NE>(tp, lane);
-      if (writer) acc[g * NE + my_e] += r;
+      if (active) {
+        const GateRef gr = A.gates[g];
+        ccoef_t<R> *co = coef + int64_t(gr.inst) * kCoefStride;
+        const cx<R> *ph = phb + buf * NA * 64 + lane;
+        R tp[NE];
+        // -0: the first fma into each partial folds into a multiply
+        static_for<0, NE>([&](auto E) __attribute__((always_inline)) { tp[CV(E)] = R(-0.0); });
+        dispatch<0, K::n>(gate_code(MODE, NT, gr, pi), [&](auto CC) __attribute__((always_inline)) {
+          contract_gate<R, NT, MODE, CV(CC), NE>(ps, ph, tp);
+          fwd_gate<R, NT, MODE, false, CV(CC)>(ps, ps, co);
+        });
+        const double r = wave_reduce_scatter<R, NE>(tp, lane);
+        if (writer) acc[g * NE + my_e] += r;
+      }
       buf ^= 1;
     }
     if (ok && active) {

@@ -40,10 +40,10 @@ def test_measured_traffic_lookup():
         assert v is None or v >= 0.9 * 6 * 2**30, (key, v)
     # Hessian sweeps (keyed on the Hessian kernel source): at least the
     # slices written per launch (8 slices x 2^15 rows x 1024 columns: 2 GiB
-    # in complex64, 4 GiB in complex128; configuration 4: 16 slices x 2^16
-    # rows, 8 GiB)
+    # in complex64, 4 GiB in complex128; 6 slices with particle-number gates,
+    # 1.5 GiB; configuration 4: 16 slices x 2^16 rows, 8 GiB)
     for key, least in (("cfg3:hess/sweep", 2 * 2**30), ("cfg3c128:hess/sweep", 4 * 2**30),
-                       ("cfg4:hess/sweep", 8 * 2**30)):
+                       ("cfg3num:hess/sweep", 1.5 * 2**30), ("cfg4:hess/sweep", 8 * 2**30)):
         v = bench.measured_traffic(key, "hess")
         assert v is None or v >= 0.99 * least, (key, v)
 
